@@ -1,0 +1,172 @@
+/*
+ * bpm.h -- C ABI of the MI355X beam-propagation library (libbpm.so).
+ *
+ * The library marches a complex light field slice by slice through a
+ * refractive-index volume with the split-step beam-propagation method using
+ * the exact (non-paraxial) propagator (Weigert, Myers & Kreysing, "Biobeam",
+ * arXiv 1706.02261, main text, paragraph on the beam-propagation model and
+ * the multiplexed PSF calculation).  One step j = 0 .. steps-1 is
+ *
+ *     v       = IDFT2( H . DFT2(u_j) ),
+ *     H[l][m] = exp(i dz sqrt(k^2 - kx^2 - ky^2))  where kx^2 + ky^2 <= k^2, else 0,
+ *     u_{j+1} = exp(i k0 dz dn[j]) . v,
+ *     I[j]    = |u_{j+1}|^2,
+ *
+ * with k0 = 2 pi / wavelength, k = n0 k0, kx = 2 pi m~ / (nx dx),
+ * ky = 2 pi l~ / (ny dx) (m~, l~ the signed DFT indices), DFT2 unnormalised
+ * with exp(-2 pi i ...), IDFT2 with exp(+...) and 1 / (nx ny).  The
+ * propagating test is evaluated exactly on integers:
+ * (m~ ny)^2 + (l~ nx)^2 <= (nx ny n0 dx / wavelength)^2.
+ *
+ * Conventions common to every entry point
+ *   - Lengths in micrometres; `wavelength` is the vacuum wavelength; dn = n - n0.
+ *   - Complex arrays are complex64: interleaved (re, im) float32, the memory
+ *     layout of torch.complex64.  Fields are [ny][nx], volumes are
+ *     [steps][ny][nx], x fastest, densely packed.
+ *   - Every pointer argument is a DEVICE pointer unless stated otherwise; the
+ *     caller owns all memory (inputs, outputs and the workspace).  The library
+ *     keeps no pointer after the call's stream work has completed and never
+ *     frees caller memory.
+ *   - Calls are asynchronous on `hip_stream` (a hipStream_t; NULL = the null
+ *     stream).  Argument errors are detected on the host before any launch
+ *     and leave every output untouched.  A launch failure is reported as
+ *     BPM_ERR_DEVICE; a fault inside a kernel surfaces at the caller's next
+ *     synchronising call.
+ *   - Supported lateral sizes: nx, ny powers of two in [32, 2048] (square
+ *     pixels, dy = dx).  Other sizes return BPM_ERR_UNSUPPORTED_SIZE.
+ *   - Return value: BPM_OK or a negative error code; bpm_last_error() gives a
+ *     message for the calling thread's last failed call.
+ *   - Gradients follow PyTorch's complex convention g = dL/dRe + i dL/dIm.
+ */
+#ifndef BPM_H
+#define BPM_H
+
+#include <stddef.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct {
+    float re, im;
+} bpm_c64;
+
+enum {
+    BPM_OK = 0,
+    BPM_ERR_INVALID_ARG = -1,      /* null pointer, negative count, bad flag     */
+    BPM_ERR_UNSUPPORTED_SIZE = -2, /* nx, ny not a power of two in [32, 2048]    */
+    BPM_ERR_WORKSPACE = -3,        /* workspace missing, too small or misaligned */
+    BPM_ERR_DEVICE = -4,           /* a HIP call or kernel launch failed         */
+    BPM_ERR_NOT_FINITE = -5        /* non-finite or non-positive geometry        */
+};
+
+/* Workspace flags for bpm_workspace_size. */
+enum {
+    BPM_WS_FORWARD = 0, /* bpm_propagate                                       */
+    BPM_WS_ADJOINT = 1  /* bpm_adjoint with the default checkpoint interval    */
+};
+
+/* Bytes of device workspace a call needs (alignment: 256 bytes).  Returns 0
+ * for unsupported arguments.  The forward march needs the propagator table
+ * (nx * ny complex64) and twiddle tables; the adjoint adds its checkpoints. */
+size_t bpm_workspace_size(int nx, int ny, int steps, int flags);
+
+/* Forward march (the paper's BPM with the exact propagator, main-text
+ * paragraph on the method).
+ *   field_in       [ny][nx] complex64, the field u_0 at the entry plane.
+ *   dn             [steps][ny][nx] float32, n - n0 of each slice (may be NULL
+ *                  only when steps == 0).
+ *   steps          >= 0; steps == 0 copies field_in to field_out.
+ *   dx, dz         lateral pixel and slice thickness (um); dx > 0, dz finite.
+ *   wavelength, n0 vacuum wavelength (um) and background index, both > 0.
+ *   field_out      [ny][nx] complex64, receives u_steps; may alias field_in.
+ *                  Also used as the march's working buffer.
+ *   intensity_out  [steps][ny][nx] float32 receiving I[j] = |u_{j+1}|^2, or
+ *                  NULL to skip the intensity volume.
+ *   workspace      device memory of at least
+ *                  bpm_workspace_size(nx, ny, steps, BPM_WS_FORWARD) bytes,
+ *                  256-byte aligned; rewritten by every call, so calls that
+ *                  share a workspace must not overlap in time.
+ */
+int bpm_propagate(const bpm_c64* field_in, const float* dn, int nx, int ny, int steps,
+                  double dx, double dz, double wavelength, double n0,
+                  bpm_c64* field_out, float* intensity_out,
+                  void* workspace, size_t workspace_bytes, void* hip_stream);
+
+/* One job of an uneven batch (host struct; its pointers are device pointers
+ * with the meaning and layout of bpm_propagate's arguments). */
+typedef struct {
+    const bpm_c64* field_in;
+    const float* dn;
+    int nx, ny, steps;
+    double dx, dz, wavelength, n0;
+    bpm_c64* field_out;
+    float* intensity_out;
+} bpm_job;
+
+/* Bytes of workspace for bpm_propagate_batch over `jobs` (host array). */
+size_t bpm_batch_workspace_size(const bpm_job* jobs, int n_jobs);
+
+/* Uneven batch: every job is an independent march (the paper's multiplexed
+ * fields, light-sheet positions and volumes; main-text paragraphs on
+ * multiplexing and on the light-sheet simulation), all run by ONE persistent
+ * kernel launch that pulls (job, pass, tile) work items from a device queue;
+ * per-job counters order each job's passes, so jobs of different size and
+ * depth overlap freely.  `jobs` is a host array of n_jobs >= 1 entries, each
+ * validated as in bpm_propagate; jobs must not share output buffers.
+ * Results are identical, bit for bit, to n_jobs separate bpm_propagate calls. */
+int bpm_propagate_batch(const bpm_job* jobs, int n_jobs,
+                        void* workspace, size_t workspace_bytes, void* hip_stream);
+
+/* Bytes of workspace for bpm_adjoint with an explicit checkpoint interval
+ * (0 selects ceil(sqrt(steps))). */
+size_t bpm_adjoint_workspace_size(int nx, int ny, int steps, int checkpoint_every);
+
+/* Adjoint march: gradients of a real loss L(u_steps, I) through bpm_propagate
+ * (reverse-mode differentiation of the step above).  The forward fields are
+ * not stored: the call re-runs the forward march keeping one field every
+ * `checkpoint_every` steps, then, segment by segment from the last, recomputes
+ * the segment's fields and runs the adjoint steps
+ *     g_{j+1} += 2 gI[j] u_{j+1},
+ *     grad_dn[j] = k0 dz Im(g_{j+1} conj(u_{j+1})),
+ *     g_j = IDFT2( conj(H) . DFT2( exp(-i k0 dz dn[j]) g_{j+1} ) ).
+ *   grad_field_out   [ny][nx] dL/du_steps, or NULL (zero).
+ *   grad_intensity   [steps][ny][nx] float32 dL/dI, or NULL (zero).
+ *   grad_field_in    [ny][nx] receives dL/du_0, or NULL.
+ *   grad_spectrum_in [ny][nx] receives dL/dU_0 for u_0 = IDFT2(U_0), i.e.
+ *                    DFT2(g_0) / (nx ny) in natural DFT order, or NULL; this
+ *                    is the pupil-plane gradient used for adaptive optics.
+ *   grad_dn          [steps][ny][nx] receives dL/ddn, or NULL.
+ *   checkpoint_every 0 (= ceil(sqrt(steps))) or 1 .. steps.
+ * Other arguments as in bpm_propagate.  Results do not depend on
+ * checkpoint_every (bitwise). */
+int bpm_adjoint(const bpm_c64* field_in, const float* dn, int nx, int ny, int steps,
+                double dx, double dz, double wavelength, double n0,
+                const bpm_c64* grad_field_out, const float* grad_intensity,
+                bpm_c64* grad_field_in, bpm_c64* grad_spectrum_in, float* grad_dn,
+                int checkpoint_every, void* workspace, size_t workspace_bytes,
+                void* hip_stream);
+
+/* Learned PSF surrogate, inference (the paper's sets of 10^5 - 10^6 spatially
+ * varying PSFs, abstract and main-text paragraph on image formation).
+ *   weights_bf16   device blob written by the surrogate trainer (format in
+ *                  the header at its start), weights_bytes its size.
+ *   dn_patches     [batch][64][32][32] float32 local dn patches (z, y, x).
+ *   depth          [batch] float32 source depth in slices (0 .. 63).
+ *   psf_out        [batch][32][32][32] float32 PSF intensity (z, y, x).
+ *   pred_err       [batch] float32 predicted relative L2 error of each PSF.
+ * BF16 operands, FP32 accumulation on the matrix cores. */
+int psf_surrogate_infer(const void* weights_bf16, size_t weights_bytes,
+                        const float* dn_patches, const float* depth, int batch,
+                        float* psf_out, float* pred_err, void* hip_stream);
+
+/* Static text for an error code. */
+const char* bpm_error_string(int code);
+/* Message of the calling thread's last failed call ("" if none). */
+const char* bpm_last_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* BPM_H */

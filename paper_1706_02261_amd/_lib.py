@@ -1,0 +1,89 @@
+"""ctypes loader of libbpm.so and the declarations of include/bpm.h.
+
+The library is the product path: when it is missing this module raises, and
+nothing falls back to another implementation.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libbpm.so")
+
+BPM_OK = 0
+BPM_ERR_INVALID_ARG = -1
+BPM_ERR_UNSUPPORTED_SIZE = -2
+BPM_ERR_WORKSPACE = -3
+BPM_ERR_DEVICE = -4
+BPM_ERR_NOT_FINITE = -5
+BPM_WS_FORWARD = 0
+BPM_WS_ADJOINT = 1
+
+# every symbol include/bpm.h declares
+EXPORTS = (
+    "bpm_workspace_size", "bpm_propagate", "bpm_batch_workspace_size",
+    "bpm_propagate_batch", "bpm_adjoint_workspace_size", "bpm_adjoint",
+    "psf_surrogate_infer", "bpm_error_string", "bpm_last_error",
+)
+
+
+class BpmError(RuntimeError):
+    def __init__(self, code: int, message: str):
+        super().__init__(message)
+        self.code = code
+
+
+class Job(ctypes.Structure):
+    """Mirror of ``bpm_job``."""
+    _fields_ = [("field_in", ctypes.c_void_p), ("dn", ctypes.c_void_p),
+                ("nx", ctypes.c_int), ("ny", ctypes.c_int), ("steps", ctypes.c_int),
+                ("dx", ctypes.c_double), ("dz", ctypes.c_double),
+                ("wavelength", ctypes.c_double), ("n0", ctypes.c_double),
+                ("field_out", ctypes.c_void_p), ("intensity_out", ctypes.c_void_p)]
+
+
+_lib = None
+_V, _I, _D, _Z, _S = ctypes.c_void_p, ctypes.c_int, ctypes.c_double, ctypes.c_size_t, ctypes.c_char_p
+
+
+def _declare(L):
+    L.bpm_workspace_size.argtypes = [_I, _I, _I, _I]
+    L.bpm_workspace_size.restype = _Z
+    L.bpm_propagate.argtypes = [_V, _V, _I, _I, _I, _D, _D, _D, _D, _V, _V, _V, _Z, _V]
+    L.bpm_propagate.restype = _I
+    L.bpm_batch_workspace_size.argtypes = [ctypes.POINTER(Job), _I]
+    L.bpm_batch_workspace_size.restype = _Z
+    L.bpm_propagate_batch.argtypes = [ctypes.POINTER(Job), _I, _V, _Z, _V]
+    L.bpm_propagate_batch.restype = _I
+    L.bpm_adjoint_workspace_size.argtypes = [_I, _I, _I, _I]
+    L.bpm_adjoint_workspace_size.restype = _Z
+    L.bpm_adjoint.argtypes = [_V, _V, _I, _I, _I, _D, _D, _D, _D, _V, _V, _V, _V, _V, _I,
+                              _V, _Z, _V]
+    L.bpm_adjoint.restype = _I
+    L.psf_surrogate_infer.argtypes = [_V, _Z, _V, _V, _I, _V, _V, _V]
+    L.psf_surrogate_infer.restype = _I
+    L.bpm_error_string.argtypes = [_I]
+    L.bpm_error_string.restype = _S
+    L.bpm_last_error.argtypes = []
+    L.bpm_last_error.restype = _S
+
+
+def lib():
+    """The loaded library; raises if it has not been built."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise RuntimeError(f"{LIB_PATH} is missing: build it with "
+                               "`python -c 'import __graft_entry__ as g; g.build()'`")
+        L = ctypes.CDLL(LIB_PATH)
+        _declare(L)
+        _lib = L
+    return _lib
+
+
+def check(rc: int, name: str) -> None:
+    if rc != BPM_OK:
+        L = lib()
+        msg = L.bpm_last_error().decode(errors="replace")
+        raise BpmError(rc, f"{name}: {L.bpm_error_string(rc).decode()} ({msg})")
