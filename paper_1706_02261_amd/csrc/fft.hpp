@@ -211,31 +211,57 @@ __device__ __forceinline__ void dft_groups(float2 (&v)[R]) {
 }
 
 // ---------------------------------------------------------------------------
+// per-thread twiddles
+//
+// Stage s < S-1 multiplies output m of its group by W^(tp m) with tp fixed per
+// thread (tp = tau for stage 0; every intermediate stage has one group per
+// thread).  A thread's twiddles therefore never change: they are fetched once
+// from the fp32 table tw[e] = exp(-2 pi i e / N) (rounded from fp64) and kept
+// in registers.
+
+template <int N, int R>
+struct Twiddles {
+    static constexpr int S = fft_num_stages(N, R);
+    static constexpr int NS = S > 1 ? S - 1 : 1;  // stages that apply twiddles
+    float2 w[NS][R];                              // w[s][m]; m = 0 is 1 and unused
+
+    __device__ __forceinline__ void load(const float2* __restrict__ tw, int tau) {
+#pragma unroll
+        for (int s = 0; s < NS; ++s) {
+            const int ta = fft_t_after(N, R, s);
+            const int tp = s == 0 ? tau : tau % ta;
+            const int step = N / (fft_radix(N, R, s) * ta);
+#pragma unroll
+            for (int m = 0; m < R; ++m) w[s][m] = m ? tw[(tp * m * step) & (N - 1)] : make_float2(1.f, 0.f);
+        }
+    }
+};
+
+// ---------------------------------------------------------------------------
 // block transforms
 //
 // lds: this transform's region; position p lives at lds[lds_pad(p) * LSTRIDE].
-// sync(): barrier over every thread that shares the LDS region.  Within one
-// stage every slot is read and rewritten by the same thread, so a barrier is
+// sync(): ordering point over every thread that shares the LDS region.  Within
+// one stage every slot is read and rewritten by the same thread, so a sync is
 // only needed after each LDS write phase.
 
 // Forward transform (exp(-...)).  In: v[i] = x[i*T + tau], natural order.
-// Out: v[reg] = X[freq_of_pos(pos_of_reg(tau, reg))].
+// Out: v[reg] = X[fft_freq_of_pos(pos_of_reg(tau, reg))].
 template <int N, int R, int LSTRIDE, typename Sync>
 __device__ __forceinline__ void fft_forward(float2 (&v)[R], float2* lds, int tau,
-                                            const float2* __restrict__ tw, Sync&& sync) {
+                                            const Twiddles<N, R>& tw, Sync sync) {
     using L = FftLayout<N, R>;
     constexpr int T = L::T;
     dft_reg<R, -1>(v);
     if constexpr (L::S > 1) {
 #pragma unroll
-        for (int k = 1; k < R; ++k) v[k] = c_mul(v[k], tw[(tau * k) & (N - 1)]);
+        for (int k = 1; k < R; ++k) v[k] = c_mul(v[k], tw.w[0][k]);
 #pragma unroll
         for (int k = 0; k < R; ++k) lds[lds_pad(k * T + tau) * LSTRIDE] = v[k];
         sync();
         static_for<1, L::S>([&](auto sc) {
             constexpr int s = decltype(sc)::value;
             constexpr int r = L::radix(s), ta = L::t_after(s), groups = R / r;
-            constexpr int twstep = N / (r * ta);
 #pragma unroll
             for (int q = 0; q < groups; ++q) {
                 const int g = tau + T * q, base = (g / ta) * r * ta + g % ta;
@@ -244,15 +270,11 @@ __device__ __forceinline__ void fft_forward(float2 (&v)[R], float2* lds, int tau
             }
             dft_groups<r, -1>(v);
             if constexpr (s < L::S - 1) {
+                const int base = (tau / ta) * r * ta + tau % ta;  // one group per thread
 #pragma unroll
-                for (int q = 0; q < groups; ++q) {
-                    const int g = tau + T * q, tp = g % ta, base = (g / ta) * r * ta + tp;
-#pragma unroll
-                    for (int m = 0; m < r; ++m) {
-                        float2 z = v[q * r + m];
-                        if (m) z = c_mul(z, tw[(tp * m * twstep) & (N - 1)]);
-                        lds[lds_pad(base + m * ta) * LSTRIDE] = z;
-                    }
+                for (int m = 0; m < r; ++m) {
+                    const float2 z = m ? c_mul(v[m], tw.w[s][m]) : v[m];
+                    lds[lds_pad(base + m * ta) * LSTRIDE] = z;
                 }
                 sync();
             }
@@ -264,24 +286,19 @@ __device__ __forceinline__ void fft_forward(float2 (&v)[R], float2* lds, int tau
 // In: the forward's output layout.  Out: v[i] = N * x[i*T + tau].
 template <int N, int R, int LSTRIDE, typename Sync>
 __device__ __forceinline__ void fft_inverse(float2 (&v)[R], float2* lds, int tau,
-                                            const float2* __restrict__ tw, Sync&& sync) {
+                                            const Twiddles<N, R>& tw, Sync sync) {
     using L = FftLayout<N, R>;
     constexpr int T = L::T;
     if constexpr (L::S > 1) {
         static_for<1, L::S>([&](auto ic) {
             constexpr int s = L::S - decltype(ic)::value;  // S-1 down to 1
             constexpr int r = L::radix(s), ta = L::t_after(s), groups = R / r;
-            constexpr int twstep = N / (r * ta);
             if constexpr (s < L::S - 1) {
+                const int base = (tau / ta) * r * ta + tau % ta;  // one group per thread
 #pragma unroll
-                for (int q = 0; q < groups; ++q) {
-                    const int g = tau + T * q, tp = g % ta, base = (g / ta) * r * ta + tp;
-#pragma unroll
-                    for (int m = 0; m < r; ++m) {
-                        float2 z = lds[lds_pad(base + m * ta) * LSTRIDE];
-                        if (m) z = c_mulc(z, tw[(tp * m * twstep) & (N - 1)]);
-                        v[q * r + m] = z;
-                    }
+                for (int m = 0; m < r; ++m) {
+                    const float2 z = lds[lds_pad(base + m * ta) * LSTRIDE];
+                    v[m] = m ? c_mulc(z, tw.w[s][m]) : z;
                 }
             }
             dft_groups<r, +1>(v);
@@ -296,7 +313,7 @@ __device__ __forceinline__ void fft_inverse(float2 (&v)[R], float2* lds, int tau
 #pragma unroll
         for (int k = 0; k < R; ++k) v[k] = lds[lds_pad(k * T + tau) * LSTRIDE];
 #pragma unroll
-        for (int k = 1; k < R; ++k) v[k] = c_mulc(v[k], tw[(tau * k) & (N - 1)]);
+        for (int k = 1; k < R; ++k) v[k] = c_mulc(v[k], tw.w[0][k]);
     }
     dft_reg<R, +1>(v);
 }

@@ -23,6 +23,7 @@ struct Plan {
     void* H;      // float2 [ny][nx]
     void* twx;    // float2 [nx]
     void* twy;    // float2 [ny]
+    void* counter;  // grid-barrier words and time-out flag (4 KiB, zeroed by the plan)
 };
 size_t plan_bytes(int nx, int ny);
 Plan plan_carve(void* ws, int nx, int ny);

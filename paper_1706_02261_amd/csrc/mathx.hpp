@@ -5,20 +5,9 @@
 
 namespace bpm {
 
-// (cos x, sin x) in fp32 for |x| up to ~1e4.
-//
-// Cody-Waite reduction x = q (pi/2) + r with a two-term pi/2 (the fp32
-// nearest value plus its residual), then the Taylor series of sin and cos on
-// |r| <= pi/4, truncated after r^9 and r^10 (remainders < 2e-11 and < 2e-9),
-// and the quadrant rotation by q.  The screen phases of the march are
-// k0 dz dn, a fraction of a radian, so q is almost always 0.
-__device__ __forceinline__ float2 expi(float x) {
-    constexpr float kTwoOverPi = 0.636619772367581343f;
-    constexpr float kPio2Hi = 1.57079637050628662109375f;      // fp32(pi/2)
-    constexpr float kPio2Lo = -4.37113900018624283e-8f;        // pi/2 - kPio2Hi
-    const float q = rintf(x * kTwoOverPi);
-    float r = fmaf(q, -kPio2Hi, x);
-    r = fmaf(q, -kPio2Lo, r);
+// (cos r, sin r) for |r| <= pi/4: Taylor series of sin and cos truncated
+// after r^9 and r^10 (remainders below 2e-11 and 2e-9 on that interval).
+__device__ __forceinline__ float2 cos_sin_quarter(float r) {
     const float r2 = r * r;
     // sin r = r (1 - r^2/3! + r^4/5! - r^6/7! + r^8/9!)
     float ps = fmaf(r2, 2.75573192239858906526e-6f, -1.98412698412698412698e-4f);
@@ -31,6 +20,23 @@ __device__ __forceinline__ float2 expi(float x) {
     pc = fmaf(r2, pc, 4.16666666666666666667e-2f);
     pc = fmaf(r2, pc, -0.5f);
     const float c = fmaf(r2, pc, 1.0f);
+    return make_float2(c, s);
+}
+
+constexpr float kQuarterPi = 0.785398163397448309616f;
+
+// (cos x, sin x) in fp32 for |x| up to ~1e4: Cody-Waite reduction
+// x = q (pi/2) + r with a two-term pi/2 (the fp32 nearest value plus its
+// residual), cos_sin_quarter(r), then the quadrant rotation by q.
+__device__ __forceinline__ float2 expi(float x) {
+    constexpr float kTwoOverPi = 0.636619772367581343f;
+    constexpr float kPio2Hi = 1.57079637050628662109375f;      // fp32(pi/2)
+    constexpr float kPio2Lo = -4.37113900018624283e-8f;        // pi/2 - kPio2Hi
+    const float q = rintf(x * kTwoOverPi);
+    float r = fmaf(q, -kPio2Hi, x);
+    r = fmaf(q, -kPio2Lo, r);
+    const float2 cs0 = cos_sin_quarter(r);
+    const float c = cs0.x, s = cs0.y;
     const int iq = static_cast<int>(q) & 3;
     const float cs = (iq & 1) ? s : c;   // |cos x| candidate
     const float sn = (iq & 1) ? c : s;   // |sin x| candidate

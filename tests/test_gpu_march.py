@@ -114,3 +114,17 @@ def test_deterministic_repeat():
     a, ia = gpu_march(u0, dn, g)
     b, ib = gpu_march(u0, dn, g)
     assert np.array_equal(a, b) and np.array_equal(ia, ib)
+
+
+@pytest.mark.parametrize("amp", [0.3, 3.0, 40.0])
+def test_large_and_negative_phases(amp):
+    """dn uniform in [-amp, amp]: screen phases k0 dz dn up to ~100 rad take the
+    range-reduced sine/cosine path."""
+    rng = np.random.default_rng(int(amp * 10))
+    g = synth.Geometry(64, 128, 4, 0.2, 0.2)
+    u0 = (rng.standard_normal((128, 64)) + 1j * rng.standard_normal((128, 64))).astype(np.complex64)
+    dn = rng.uniform(-amp, amp, (4, 128, 64)).astype(np.float32)
+    u, inten = gpu_march(u0, dn, g)
+    ru, ri = ora_march(u0, dn, g)
+    tol = 2e-6 * max(1.0, amp)      # fp32 phase k0 dz dn carries ~6e-8 relative error
+    assert rel(u, ru) <= tol and rel(inten, ri) <= tol
