@@ -1,0 +1,192 @@
+#!/usr/bin/env python3
+"""Benchmark of the split-step beam-propagation march on one MI355X.
+
+Timed step: one paper-scale detection march -- a 1024 x 1024 complex64 field
+carrying 1000 multiplexed NA 0.6 point sources through 1024 slices of an
+embryo-like ellipsoid phantom (dx = dz = 0.2 um, lambda = 0.5 um, n0 = 1.33),
+intensity volume written -- through the C ABI (bpm_propagate), inputs resident
+in HBM.  Prints ONE JSON line:
+
+  value      Gvoxel-steps/s = nx * ny * slices / t_march
+  roofline   HBM model: 40 bytes per voxel-step (two read+write passes over
+             the complex64 field, the dn slice read, the intensity write)
+             against 8 TB/s; `traffic` is the rocprofv3-measured HBM traffic
+             per launch when the committed counter summary matches the
+             current kernel source, else null
+  cpu_baseline  the FP64 oracle on the machine's host cores over a bounded sample
+             (the first slices of the same volume), with the relative L2
+             error of the GPU field against it on that sample
+
+`--gpus N` with N > 1 exits: this build runs on one GPU.
+"""
+from __future__ import annotations
+
+import argparse
+import hashlib
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+METRIC = "BPM Gvoxel-steps/s at 1024³ c64 (% HBM roofline); surrogate vs BPM PSFs/s"
+HBM_PEAK_GBS = 8000.0
+FP32_PEAK_TFLOPS = 157.3
+BYTES_PER_VOXEL_STEP = 40
+FLOP_PER_VOXEL_STEP = 215          # 10 log2(nx ny) + 15 at 1024^2 (5 N log2 N FFT count)
+PAPER_GVS = 1024 ** 3 / 0.5 / 1e9  # < 500 ms for 1024^3 voxels, main text
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "march_1024cube_traffic.json")
+
+
+def kernel_source_hash() -> str:
+    h = hashlib.sha256()
+    csrc = os.path.join(ROOT, "paper_1706_02261_amd", "csrc")
+    for name in sorted(os.listdir(csrc)):
+        if name.endswith((".hip", ".hpp")):
+            with open(os.path.join(csrc, name), "rb") as f:
+                h.update(name.encode() + b"\0" + f.read())
+    return h.hexdigest()[:16]
+
+
+def measured_traffic():
+    """HBM bytes per launch from the committed rocprofv3 summary, if it was
+    taken on the current kernel source."""
+    try:
+        with open(TRAFFIC_FILE) as f:
+            t = json.load(f)
+    except (OSError, ValueError):
+        return None
+    if t.get("source_hash") != kernel_source_hash():
+        return None
+    return t.get("bytes_per_launch")
+
+
+def cpu_baseline(u0, dn_host, g, gpu_fn, target_s=15.0):
+    import numpy as np
+    import oracle
+    threads = oracle.set_threads(0)
+    probe = 2
+    t0 = time.perf_counter()
+    oracle.bpm_forward(u0, dn_host[:probe], g.dx, g.dz, g.wavelength, g.n0, intensity=False)
+    per_step = (time.perf_counter() - t0) / probe
+    steps = int(max(4, min(dn_host.shape[0], target_s / max(per_step, 1e-6))))
+    t0 = time.perf_counter()
+    ref, _ = oracle.bpm_forward(u0, dn_host[:steps], g.dx, g.dz, g.wavelength, g.n0,
+                                intensity=False)
+    t = time.perf_counter() - t0
+    got = gpu_fn(steps)
+    err = float(np.linalg.norm(got - ref) / np.linalg.norm(ref))
+    return {"value": round(g.nx * g.ny * steps / t / 1e9, 4), "unit": "Gvoxel-steps/s",
+            "cores": threads, "kind": "oracle",
+            "sample": f"{g.nx}x{g.ny} field, first {steps} of {g.steps} slices of the timed "
+                      f"volume, FP64 radix-2 oracle, OpenMP {threads} threads, "
+                      f"{t:.1f} s",
+            "gpu_rel_l2_err_on_sample": err}
+
+
+def main():
+    ap = argparse.ArgumentParser(description=__doc__.split("\n\n")[0])
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=10, help="timed marches")
+    ap.add_argument("--warmup", type=int, default=2, help="untimed marches")
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--slices", type=int, default=1024, help="march depth (default 1024)")
+    args = ap.parse_args()
+    world = int(os.environ.get("WORLD_SIZE", "1"))
+    if args.gpus != 1 or world != 1:
+        print(f"bench.py: this build runs on one GPU; --gpus {args.gpus} (WORLD_SIZE "
+              f"{world}) is not supported", file=sys.stderr)
+        sys.exit(2)
+
+    import numpy as np
+    import torch
+
+    import paper_1706_02261_amd as bpm
+    from paper_1706_02261_amd import bpm as B
+    import synth
+
+    dev = torch.device("cuda:0")
+    t_gen = time.perf_counter()
+    g, u0, dn_host = synth.config2_detection(steps=args.slices)
+    t_gen = time.perf_counter() - t_gen
+    field = torch.from_numpy(u0).to(dev)
+    dn = torch.from_numpy(dn_host).to(dev)
+    out = torch.empty_like(field)
+    inten = torch.empty((g.steps, g.ny, g.nx), dtype=torch.float32, device=dev)
+    ws = B.workspace(B.workspace_size(g.nx, g.ny, g.steps), dev)
+    stream = torch.cuda.current_stream(dev)
+
+    def march():
+        bpm.propagate(field, dn, g.dx, g.dz, g.wavelength, g.n0, out=out,
+                      intensity_out=inten, ws=ws, stream=stream)
+
+    for _ in range(args.warmup):
+        march()
+    torch.cuda.synchronize(dev)
+    ev = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True))
+          for _ in range(args.steps)]
+    torch.cuda.synchronize(dev)
+    t0 = time.perf_counter()
+    for a, b in ev:
+        a.record(stream)
+        march()
+        b.record(stream)
+    torch.cuda.synchronize(dev)
+    wall = time.perf_counter() - t0
+    per_launch_ms = [a.elapsed_time(b) for a, b in ev]
+    ms = wall * 1e3 / args.steps
+    launch_ms = float(np.mean(per_launch_ms))
+    voxel_steps = g.nx * g.ny * g.steps
+    value = voxel_steps / (ms / 1e3) / 1e9
+    achieved = BYTES_PER_VOXEL_STEP * voxel_steps / (launch_ms / 1e3) / 1e9
+    traffic = measured_traffic()
+    line = {
+        "metric": METRIC,
+        "value": round(value, 3),
+        "unit": "Gvoxel-steps/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": round(ms, 4),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": round(value / PAPER_GVS, 2),
+        "dtype": "f32",
+        "data": "synthetic",
+        "config": {
+            "workload": f"paper-scale detection march: {g.nx}x{g.ny} complex64 field, "
+                        f"{g.steps} slices, dx=dz=0.2 um, lambda=0.5 um, n0=1.33, 1000 "
+                        "multiplexed NA 0.6 point sources, embryo-like ellipsoid phantom "
+                        "(n 1.33-1.38), intensity volume written",
+            "nx": g.nx, "ny": g.ny, "slices": g.steps, "sources": 1000,
+        },
+        "roofline": {
+            "bound": "hbm",
+            "achieved": round(achieved, 1),
+            "peak": HBM_PEAK_GBS,
+            "unit": "GB/s",
+            "frac": round(achieved / HBM_PEAK_GBS, 4),
+            "traffic": traffic,
+            "kernel": "march_kernel (one launch per march, plan kernel included)",
+            "launch_ms": round(launch_ms, 4),
+            "bytes_per_voxel_step": BYTES_PER_VOXEL_STEP,
+            "fp32_tflops": round(FLOP_PER_VOXEL_STEP * voxel_steps / (launch_ms / 1e3) / 1e12, 2),
+            "fp32_frac": round(FLOP_PER_VOXEL_STEP * voxel_steps / (launch_ms / 1e3) / 1e12
+                               / FP32_PEAK_TFLOPS, 4),
+        },
+        "input_generation_s": round(t_gen, 1),
+    }
+    if not args.no_cpu_baseline:
+        def gpu_first(steps):
+            o, _ = bpm.propagate(field, dn[:steps].contiguous(), g.dx, g.dz, g.wavelength,
+                                 g.n0, intensity=False)
+            torch.cuda.synchronize(dev)
+            return o.cpu().numpy()
+        line["cpu_baseline"] = cpu_baseline(u0, dn_host, g, gpu_first)
+    print(json.dumps(line), flush=True)
+
+
+if __name__ == "__main__":
+    main()
