@@ -147,6 +147,32 @@ int bpm_adjoint(const bpm_c64* field_in, const float* dn, int nx, int ny, int st
                 int checkpoint_every, void* workspace, size_t workspace_bytes,
                 void* hip_stream);
 
+/* Bytes of workspace for bpm_fft2. */
+size_t bpm_fft2_workspace_size(int nx, int ny);
+
+/* Natural-order 2-D DFT of a [ny][nx] complex64 array (helper of the pupil
+ * plane; the march itself never leaves its own storage order).  inverse = 0:
+ * X[l][m] = sum x[y][x] exp(-2 pi i (m x / nx + l y / ny)), unnormalised;
+ * inverse = 1: exp(+...) and 1 / (nx ny).  `out` may alias `in`.  Workspace:
+ * bpm_fft2_workspace_size bytes, 256-byte aligned. */
+int bpm_fft2(const bpm_c64* in, bpm_c64* out, int nx, int ny, int inverse,
+             void* workspace, size_t workspace_bytes, void* hip_stream);
+
+/* Pupil-plane field of the adaptive-optics problem (the paper's guide-star
+ * wavefront conjugation, main-text paragraph on adaptive optics): the angular
+ * spectrum U0[l][m] = A exp(i phi) exp(-i kz z_focus), natural DFT order, with
+ * kz = sqrt(k^2 - kx^2 - ky^2) (0 where evanescent) and k = 2 pi n0 /
+ * wavelength.  amplitude and phase are [ny][nx] float32; the entry field of
+ * the march is bpm_fft2(U0, inverse = 1). */
+int bpm_pupil_spectrum(const float* amplitude, const float* phase, int nx, int ny, double dx,
+                       double wavelength, double n0, double z_focus, bpm_c64* spectrum_out,
+                       void* hip_stream);
+
+/* dL/dphi = Im(dL/dU0 * conj(U0)) from bpm_adjoint's grad_spectrum_in and the
+ * spectrum U0 of bpm_pupil_spectrum ([ny][nx] each; grad_phase float32). */
+int bpm_pupil_phase_grad(const bpm_c64* grad_spectrum, const bpm_c64* spectrum, int nx, int ny,
+                         float* grad_phase, void* hip_stream);
+
 /* Learned PSF surrogate, inference (the paper's sets of 10^5 - 10^6 spatially
  * varying PSFs, abstract and main-text paragraph on image formation).
  *   weights_bf16   device blob written by the surrogate trainer (format in

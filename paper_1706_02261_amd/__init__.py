@@ -5,6 +5,8 @@ runs in the library's HIP kernels; this package only checks and marshals
 torch tensors (device memory and streams) into the C ABI.
 """
 from ._lib import BpmError, lib  # noqa: F401
-from .bpm import propagate, workspace_size  # noqa: F401
+from .bpm import (BPMFunction, PupilBPMFunction, adjoint, fft2, propagate,  # noqa: F401
+                  pupil_phase_grad, pupil_spectrum, workspace_size)
 
-__all__ = ["BpmError", "lib", "propagate", "workspace_size"]
+__all__ = ["BpmError", "lib", "propagate", "adjoint", "fft2", "pupil_spectrum",
+           "pupil_phase_grad", "BPMFunction", "PupilBPMFunction", "workspace_size"]

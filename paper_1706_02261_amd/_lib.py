@@ -25,6 +25,7 @@ EXPORTS = (
     "bpm_workspace_size", "bpm_propagate", "bpm_batch_workspace_size",
     "bpm_propagate_batch", "bpm_adjoint_workspace_size", "bpm_adjoint",
     "psf_surrogate_infer", "bpm_error_string", "bpm_last_error",
+    "bpm_fft2_workspace_size", "bpm_fft2", "bpm_pupil_spectrum", "bpm_pupil_phase_grad",
 )
 
 
@@ -63,6 +64,14 @@ def _declare(L):
     L.bpm_adjoint.restype = _I
     L.psf_surrogate_infer.argtypes = [_V, _Z, _V, _V, _I, _V, _V, _V]
     L.psf_surrogate_infer.restype = _I
+    L.bpm_fft2_workspace_size.argtypes = [_I, _I]
+    L.bpm_fft2_workspace_size.restype = _Z
+    L.bpm_fft2.argtypes = [_V, _V, _I, _I, _I, _V, _Z, _V]
+    L.bpm_fft2.restype = _I
+    L.bpm_pupil_spectrum.argtypes = [_V, _V, _I, _I, _D, _D, _D, _D, _V, _V]
+    L.bpm_pupil_spectrum.restype = _I
+    L.bpm_pupil_phase_grad.argtypes = [_V, _V, _I, _I, _V, _V]
+    L.bpm_pupil_phase_grad.restype = _I
     L.bpm_error_string.argtypes = [_I]
     L.bpm_error_string.restype = _S
     L.bpm_last_error.argtypes = []

@@ -75,3 +75,141 @@ def propagate(field: torch.Tensor, dn: torch.Tensor, dx: float, dz: float,
                              _ptr(ws), ws.numel(), _stream_ptr(stream))
     check(rc, "bpm_propagate")
     return out, intensity_out
+
+
+def adjoint_workspace_size(nx: int, ny: int, steps: int, checkpoint_every: int = 0) -> int:
+    n = lib().bpm_adjoint_workspace_size(nx, ny, steps, checkpoint_every)
+    if n == 0:
+        raise _lib.BpmError(_lib.BPM_ERR_INVALID_ARG,
+                            f"no adjoint workspace for nx={nx} ny={ny} steps={steps} "
+                            f"checkpoint_every={checkpoint_every}")
+    return int(n)
+
+
+def adjoint(field: torch.Tensor, dn: torch.Tensor, dx: float, dz: float, wavelength: float,
+            n0: float, grad_field_out: torch.Tensor | None = None,
+            grad_intensity: torch.Tensor | None = None, want_field: bool = True,
+            want_spectrum: bool = False, want_dn: bool = True, checkpoint_every: int = 0,
+            ws: torch.Tensor | None = None, stream=None):
+    """Gradients through ``propagate`` (PyTorch's complex convention).
+
+    Returns ``(grad_field_in, grad_spectrum_in, grad_dn)`` with None for the
+    ones not requested."""
+    _need(field, "field", torch.complex64)
+    ny, nx = field.shape
+    _need(dn, "dn", torch.float32)
+    if dn.dim() != 3 or tuple(dn.shape[1:]) != (ny, nx):
+        raise ValueError(f"dn has shape {tuple(dn.shape)}, expected [steps][{ny}][{nx}]")
+    steps = dn.shape[0]
+    if grad_field_out is not None:
+        _need(grad_field_out, "grad_field_out", torch.complex64, (ny, nx))
+    if grad_intensity is not None:
+        _need(grad_intensity, "grad_intensity", torch.float32, (steps, ny, nx))
+    dev = field.device
+    g0 = torch.empty_like(field) if want_field else None
+    gs = torch.empty_like(field) if want_spectrum else None
+    gdn = torch.empty((steps, ny, nx), dtype=torch.float32, device=dev) if want_dn else None
+    need = adjoint_workspace_size(nx, ny, steps, checkpoint_every)
+    if ws is None:
+        ws = workspace(need, dev)
+    rc = lib().bpm_adjoint(_ptr(field), _ptr(dn), nx, ny, steps, float(dx), float(dz),
+                           float(wavelength), float(n0), _ptr(grad_field_out),
+                           _ptr(grad_intensity), _ptr(g0), _ptr(gs), _ptr(gdn),
+                           int(checkpoint_every), _ptr(ws), ws.numel(), _stream_ptr(stream))
+    check(rc, "bpm_adjoint")
+    return g0, gs, gdn
+
+
+def fft2(x: torch.Tensor, inverse: bool = False, out: torch.Tensor | None = None, stream=None):
+    """Natural-order 2-D DFT (numpy's fft2 / ifft2 conventions) of a complex64 [ny][nx]."""
+    _need(x, "x", torch.complex64)
+    ny, nx = x.shape
+    if out is None:
+        out = torch.empty_like(x)
+    _need(out, "out", torch.complex64, (ny, nx))
+    ws = workspace(lib().bpm_fft2_workspace_size(nx, ny), x.device)
+    rc = lib().bpm_fft2(_ptr(x), _ptr(out), nx, ny, 1 if inverse else 0, _ptr(ws), ws.numel(),
+                        _stream_ptr(stream))
+    check(rc, "bpm_fft2")
+    return out
+
+
+def pupil_spectrum(amplitude: torch.Tensor, phase: torch.Tensor, dx: float, wavelength: float,
+                   n0: float, z_focus: float, stream=None) -> torch.Tensor:
+    """U0 = A exp(i phi) exp(-i kz z_focus) on the natural DFT grid."""
+    _need(amplitude, "amplitude", torch.float32)
+    ny, nx = amplitude.shape
+    _need(phase, "phase", torch.float32, (ny, nx))
+    out = torch.empty((ny, nx), dtype=torch.complex64, device=amplitude.device)
+    rc = lib().bpm_pupil_spectrum(_ptr(amplitude), _ptr(phase), nx, ny, float(dx),
+                                  float(wavelength), float(n0), float(z_focus), _ptr(out),
+                                  _stream_ptr(stream))
+    check(rc, "bpm_pupil_spectrum")
+    return out
+
+
+def pupil_phase_grad(grad_spectrum: torch.Tensor, spectrum: torch.Tensor, stream=None):
+    """dL/dphi = Im(dL/dU0 conj(U0))."""
+    _need(spectrum, "spectrum", torch.complex64)
+    ny, nx = spectrum.shape
+    _need(grad_spectrum, "grad_spectrum", torch.complex64, (ny, nx))
+    out = torch.empty((ny, nx), dtype=torch.float32, device=spectrum.device)
+    rc = lib().bpm_pupil_phase_grad(_ptr(grad_spectrum), _ptr(spectrum), nx, ny, _ptr(out),
+                                    _stream_ptr(stream))
+    check(rc, "bpm_pupil_phase_grad")
+    return out
+
+
+class BPMFunction(torch.autograd.Function):
+    """(field, dn) -> (field_out, intensity) with the hand-written adjoint march
+    (checkpointed recomputation) as backward."""
+
+    @staticmethod
+    def forward(ctx, field, dn, dx, dz, wavelength, n0, checkpoint_every=0):
+        field = field.contiguous()
+        dn = dn.contiguous()
+        out, inten = propagate(field, dn, dx, dz, wavelength, n0, intensity=True)
+        ctx.save_for_backward(field, dn)
+        ctx.geom = (dx, dz, wavelength, n0, checkpoint_every)
+        return out, inten
+
+    @staticmethod
+    def backward(ctx, g_out, g_inten):
+        field, dn = ctx.saved_tensors
+        dx, dz, wavelength, n0, ck = ctx.geom
+        g_out = None if g_out is None else g_out.contiguous()
+        g_inten = None if g_inten is None else g_inten.contiguous()
+        g0, _, gdn = adjoint(field, dn, dx, dz, wavelength, n0, grad_field_out=g_out,
+                             grad_intensity=g_inten, want_field=ctx.needs_input_grad[0],
+                             want_dn=ctx.needs_input_grad[1], checkpoint_every=ck)
+        return g0, gdn, None, None, None, None, None
+
+
+class PupilBPMFunction(torch.autograd.Function):
+    """(pupil phase, dn) -> (field_out, intensity) for the entry field
+    u0 = IDFT2(A exp(i phi) exp(-i kz z_focus)); backward gives dL/dphi (the
+    adaptive-optics correction) and dL/ddn."""
+
+    @staticmethod
+    def forward(ctx, phase, amplitude, dn, dx, dz, wavelength, n0, z_focus, checkpoint_every=0):
+        phase = phase.contiguous()
+        amplitude = amplitude.contiguous()
+        dn = dn.contiguous()
+        spec = pupil_spectrum(amplitude, phase, dx, wavelength, n0, z_focus)
+        u0 = fft2(spec, inverse=True)
+        out, inten = propagate(u0, dn, dx, dz, wavelength, n0, intensity=True)
+        ctx.save_for_backward(spec, u0, dn)
+        ctx.geom = (dx, dz, wavelength, n0, checkpoint_every)
+        return out, inten
+
+    @staticmethod
+    def backward(ctx, g_out, g_inten):
+        spec, u0, dn = ctx.saved_tensors
+        dx, dz, wavelength, n0, ck = ctx.geom
+        g_out = None if g_out is None else g_out.contiguous()
+        g_inten = None if g_inten is None else g_inten.contiguous()
+        _, gspec, gdn = adjoint(u0, dn, dx, dz, wavelength, n0, grad_field_out=g_out,
+                                grad_intensity=g_inten, want_field=False, want_spectrum=True,
+                                want_dn=ctx.needs_input_grad[2], checkpoint_every=ck)
+        gphi = pupil_phase_grad(gspec, spec) if ctx.needs_input_grad[0] else None
+        return gphi, None, gdn, None, None, None, None, None, None

@@ -105,7 +105,7 @@ int bpm_propagate(const bpm_c64* field_in, const float* dn, int nx, int ny, int 
     hipStream_t s = static_cast<hipStream_t>(hip_stream);
     const bpm::Geom g{nx, ny, steps, dx, dz, wavelength, n0};
     const bpm::Plan p = bpm::plan_carve(workspace, nx, ny);
-    if ((rc = device_status(bpm::launch_plan(g, p, s), "plan"))) return rc;
+    if ((rc = device_status(bpm::launch_plan(g, p, true, s), "plan"))) return rc;
     const bpm::MarchIO io{field_in, dn, field_out, intensity_out};
     return device_status(bpm::launch_forward(g, p, io, s), "forward march");
 }
@@ -122,9 +122,19 @@ int bpm_propagate_batch(const bpm_job* jobs, int n_jobs, void* workspace,
     return fail(BPM_ERR_INVALID_ARG, "bpm_propagate_batch: not built yet");
 }
 
+static int checkpoint_interval(int steps, int checkpoint_every) {
+    if (checkpoint_every > 0) return checkpoint_every;
+    int k = 1;
+    while (k * k < steps) ++k;
+    return k;
+}
+
 size_t bpm_adjoint_workspace_size(int nx, int ny, int steps, int checkpoint_every) {
-    (void)nx; (void)ny; (void)steps; (void)checkpoint_every;
-    return 0;
+    if (!pow2_in_range(nx) || !pow2_in_range(ny) || steps < 0 || checkpoint_every < 0) return 0;
+    if (steps > 0 && checkpoint_every > steps) return 0;
+    const size_t plane = sizeof(bpm_c64) * (size_t)nx * ny;
+    const size_t fields = steps > 0 ? bpm::adjoint_fields(steps, checkpoint_interval(steps, checkpoint_every)) : 0;
+    return bpm::plan_bytes(nx, ny) + bpm::align_up(plane * fields);
 }
 
 int bpm_adjoint(const bpm_c64* field_in, const float* dn, int nx, int ny, int steps, double dx,
@@ -132,11 +142,103 @@ int bpm_adjoint(const bpm_c64* field_in, const float* dn, int nx, int ny, int st
                 const float* grad_intensity, bpm_c64* grad_field_in, bpm_c64* grad_spectrum_in,
                 float* grad_dn, int checkpoint_every, void* workspace, size_t workspace_bytes,
                 void* hip_stream) {
-    (void)field_in; (void)dn; (void)nx; (void)ny; (void)steps; (void)dx; (void)dz;
-    (void)wavelength; (void)n0; (void)grad_field_out; (void)grad_intensity;
-    (void)grad_field_in; (void)grad_spectrum_in; (void)grad_dn; (void)checkpoint_every;
-    (void)workspace; (void)workspace_bytes; (void)hip_stream;
-    return fail(BPM_ERR_INVALID_ARG, "bpm_adjoint: not built yet");
+    int rc = check_geom(nx, ny, steps, dx, dz, wavelength, n0);
+    if (rc) return rc;
+    if (!field_in) return fail(BPM_ERR_INVALID_ARG, "field_in must be non-null");
+    if (steps > 0 && !dn) return fail(BPM_ERR_INVALID_ARG, "dn must be non-null when steps > 0");
+    if (checkpoint_every < 0 || (steps > 0 && checkpoint_every > steps))
+        return fail(BPM_ERR_INVALID_ARG, "checkpoint_every=%d must be 0 or in [1, steps=%d]",
+                    checkpoint_every, steps);
+    const void* ptrs8[] = {field_in, grad_field_out, grad_field_in, grad_spectrum_in};
+    for (const void* q : ptrs8)
+        if (q && !aligned(q, 8)) return fail(BPM_ERR_INVALID_ARG, "complex arrays must be 8-byte aligned");
+    const void* ptrs4[] = {dn, grad_intensity, grad_dn};
+    for (const void* q : ptrs4)
+        if (q && !aligned(q, 4)) return fail(BPM_ERR_INVALID_ARG, "float arrays must be 4-byte aligned");
+    const size_t need = bpm_adjoint_workspace_size(nx, ny, steps, checkpoint_every);
+    if ((rc = check_workspace(workspace, workspace_bytes, need))) return rc;
+    hipStream_t s = static_cast<hipStream_t>(hip_stream);
+    const bpm::Geom g{nx, ny, steps, dx, dz, wavelength, n0};
+    const bpm::Plan p = bpm::plan_carve(workspace, nx, ny);
+    const size_t plane = sizeof(bpm_c64) * (size_t)nx * ny;
+    if (steps == 0) {
+        // g_0 = dL/du_0 = dL/du_N; dL/dU_0 = DFT2(g_0) / (nx ny)
+        if ((rc = device_status(bpm::launch_plan(g, p, false, s), "plan"))) return rc;
+        if (grad_field_in) {
+            hipError_t e = grad_field_out
+                ? hipMemcpyAsync(grad_field_in, grad_field_out, plane, hipMemcpyDeviceToDevice, s)
+                : hipMemsetAsync(grad_field_in, 0, plane, s);
+            if ((rc = device_status(e, "copy"))) return rc;
+        }
+        if (grad_spectrum_in) {
+            hipError_t e = grad_field_out
+                ? bpm::launch_fft2(grad_field_out, grad_spectrum_in, nx, ny, false,
+                                   (float)(1.0 / ((double)nx * ny)), p, s)
+                : hipMemsetAsync(grad_spectrum_in, 0, plane, s);
+            if ((rc = device_status(e, "spectrum"))) return rc;
+        }
+        return BPM_OK;
+    }
+    if ((rc = device_status(bpm::launch_plan(g, p, true, s), "plan"))) return rc;
+    const int K = checkpoint_interval(steps, checkpoint_every);
+    void* fields = static_cast<char*>(workspace) + bpm::plan_bytes(nx, ny);
+    const bpm::AdjointIO io{field_in, dn, grad_field_out, grad_intensity, grad_field_in,
+                            grad_spectrum_in, grad_dn};
+    return device_status(bpm::launch_adjoint(g, p, io, K, fields, s), "adjoint march");
+}
+
+size_t bpm_fft2_workspace_size(int nx, int ny) {
+    if (!pow2_in_range(nx) || !pow2_in_range(ny)) return 0;
+    return bpm::plan_bytes(nx, ny);
+}
+
+int bpm_fft2(const bpm_c64* in, bpm_c64* out, int nx, int ny, int inverse, void* workspace,
+             size_t workspace_bytes, void* hip_stream) {
+    if (!pow2_in_range(nx) || !pow2_in_range(ny))
+        return fail(BPM_ERR_UNSUPPORTED_SIZE,
+                    "nx=%d ny=%d: sizes must be powers of two in [32, 2048]", nx, ny);
+    if (!in || !out) return fail(BPM_ERR_INVALID_ARG, "in and out must be non-null");
+    if (!aligned(in, 8) || !aligned(out, 8))
+        return fail(BPM_ERR_INVALID_ARG, "complex arrays must be 8-byte aligned");
+    if (inverse != 0 && inverse != 1) return fail(BPM_ERR_INVALID_ARG, "inverse must be 0 or 1");
+    int rc;
+    if ((rc = check_workspace(workspace, workspace_bytes, bpm::plan_bytes(nx, ny)))) return rc;
+    hipStream_t s = static_cast<hipStream_t>(hip_stream);
+    const bpm::Geom g{nx, ny, 0, 1.0, 0.0, 1.0, 1.0};
+    const bpm::Plan p = bpm::plan_carve(workspace, nx, ny);
+    if ((rc = device_status(bpm::launch_plan(g, p, false, s), "plan"))) return rc;
+    const float scale = inverse ? (float)(1.0 / ((double)nx * ny)) : 1.0f;
+    return device_status(bpm::launch_fft2(in, out, nx, ny, inverse != 0, scale, p, s), "fft2");
+}
+
+int bpm_pupil_spectrum(const float* amplitude, const float* phase, int nx, int ny, double dx,
+                       double wavelength, double n0, double z_focus, bpm_c64* spectrum_out,
+                       void* hip_stream) {
+    int rc = check_geom(nx, ny, 0, dx, 0.0, wavelength, n0);
+    if (rc) return rc;
+    if (!std::isfinite(z_focus)) return fail(BPM_ERR_NOT_FINITE, "z_focus must be finite");
+    if (!amplitude || !phase || !spectrum_out)
+        return fail(BPM_ERR_INVALID_ARG, "amplitude, phase and spectrum_out must be non-null");
+    if (!aligned(amplitude, 4) || !aligned(phase, 4) || !aligned(spectrum_out, 8))
+        return fail(BPM_ERR_INVALID_ARG, "misaligned array");
+    const bpm::Geom g{nx, ny, 0, dx, 0.0, wavelength, n0};
+    return device_status(bpm::launch_pupil_spectrum(amplitude, phase, g, z_focus, spectrum_out,
+                                                    static_cast<hipStream_t>(hip_stream)),
+                         "pupil spectrum");
+}
+
+int bpm_pupil_phase_grad(const bpm_c64* grad_spectrum, const bpm_c64* spectrum, int nx, int ny,
+                         float* grad_phase, void* hip_stream) {
+    if (!pow2_in_range(nx) || !pow2_in_range(ny))
+        return fail(BPM_ERR_UNSUPPORTED_SIZE,
+                    "nx=%d ny=%d: sizes must be powers of two in [32, 2048]", nx, ny);
+    if (!grad_spectrum || !spectrum || !grad_phase)
+        return fail(BPM_ERR_INVALID_ARG, "all arrays must be non-null");
+    if (!aligned(grad_spectrum, 8) || !aligned(spectrum, 8) || !aligned(grad_phase, 4))
+        return fail(BPM_ERR_INVALID_ARG, "misaligned array");
+    return device_status(bpm::launch_pupil_grad(grad_spectrum, spectrum, (long)nx * ny,
+                                                grad_phase, static_cast<hipStream_t>(hip_stream)),
+                         "pupil phase gradient");
 }
 
 int psf_surrogate_infer(const void* weights_bf16, size_t weights_bytes, const float* dn_patches,

@@ -17,17 +17,20 @@ struct Geom {
 };
 
 // Device plan of one geometry, carved out of the caller's workspace:
-// the propagator table in the march's storage order (1 / (nx ny) folded in)
-// and the two twiddle tables tw[e] = exp(-2 pi i e / n).
+// the propagator table in the march's storage order (1 / (nx ny) folded in),
+// the twiddle tables tw[e] = exp(-2 pi i e / n), the storage-slot ->
+// frequency tables of both axes and the grid-barrier words.
 struct Plan {
-    void* H;      // float2 [ny][nx]
-    void* twx;    // float2 [nx]
-    void* twy;    // float2 [ny]
+    void* H;        // float2 [ny][nx]
+    void* twx;      // float2 [nx]
+    void* twy;      // float2 [ny]
+    void* permx;    // int [nx]
+    void* permy;    // int [ny]
     void* counter;  // grid-barrier words and time-out flag (4 KiB, zeroed by the plan)
 };
 size_t plan_bytes(int nx, int ny);
 Plan plan_carve(void* ws, int nx, int ny);
-hipError_t launch_plan(const Geom& g, const Plan& p, hipStream_t s);
+hipError_t launch_plan(const Geom& g, const Plan& p, bool with_h, hipStream_t s);
 
 // Forward march through `steps` slices; field_out doubles as working buffer.
 struct MarchIO {
@@ -37,5 +40,30 @@ struct MarchIO {
     float* intensity;      // [steps][ny][nx] or nullptr
 };
 hipError_t launch_forward(const Geom& g, const Plan& p, const MarchIO& io, hipStream_t s);
+
+// Adjoint march (steps >= 1) with a checkpoint every K steps; `fields` holds
+// adjoint_fields(steps, K) fields of nx * ny complex64.
+struct AdjointIO {
+    const void* field_in;
+    const float* dn;
+    const void* grad_out;     // or nullptr
+    const float* grad_inten;  // or nullptr
+    void* grad_in;            // or nullptr
+    void* grad_spec;          // or nullptr
+    float* grad_dn;           // or nullptr
+};
+size_t adjoint_fields(int steps, int K);
+hipError_t launch_adjoint(const Geom& g, const Plan& p, const AdjointIO& io, int K, void* fields,
+                          hipStream_t s);
+
+// Natural-order 2-D DFT (exp(-) forward, exp(+) inverse, unnormalised, times
+// `scale`); needs a plan built with or without the propagator.
+hipError_t launch_fft2(const void* in, void* out, int nx, int ny, bool inverse, float scale,
+                       const Plan& p, hipStream_t s);
+
+// Pupil plane of the adaptive-optics gradient.
+hipError_t launch_pupil_spectrum(const float* amp, const float* phase, const Geom& g, double z_f,
+                                 void* U, hipStream_t s);
+hipError_t launch_pupil_grad(const void* G, const void* U, long n, float* gphi, hipStream_t s);
 
 }  // namespace bpm

@@ -1,4 +1,6 @@
-// Forward split-step march: plan builder, fused row pass, fused column pass.
+// Split-step march kernels: plan builder, fused row and column passes, the
+// persistent forward march, the persistent adjoint march with checkpointing,
+// a natural-order 2-D FFT and the pupil-plane helpers.
 //
 // One step j of the march (propagate, then phase screen) is split into two
 // passes over the field, each reading and writing it once:
@@ -10,9 +12,16 @@
 //
 // plus a head row pass (forward row FFTs of u_0) and a tail row pass (no
 // forward FFT; natural-order u_steps written out).  Between passes the field
-// lives in the caller's output buffer with its x axis in the FFT's storage
-// order (see fft.hpp); the y axis never leaves a column pass permuted.
+// lives in a working buffer with its x axis in the FFT's storage order (see
+// fft.hpp); the y axis never leaves a column pass permuted.
+//
+// The adjoint step (reverse-mode derivative of one step) has the same two
+// passes in the same order: the row pass adds 2 dL/dI u, emits
+// dL/ddn = k0 dz Im(g conj(u)) and multiplies by the conjugate screen; the
+// column pass multiplies by conj(H).
 #include <hip/hip_runtime.h>
+
+#include <type_traits>
 
 #include "fft.hpp"
 #include "internal.hpp"
@@ -20,15 +29,20 @@
 
 namespace bpm {
 
-constexpr int kR = 16;         // complex values per thread
+constexpr int kR = 16;           // complex values per thread
+constexpr int kBlock = 256;      // threads per workgroup
 constexpr int kBarWords = 1024;  // grid-barrier words (4 KiB) in the plan
 
-// The field travels between the passes of the persistent march through
-// global memory while the kernel runs.  The L2 caches of the eight XCDs are
-// not coherent with each other, so every access to that buffer is an
-// agent-scope relaxed atomic (a load that does not hit a stale L2 line, a
-// store that writes through to the device coherence point).  Read-only data
-// (propagator, twiddles, dn) keeps ordinary cached loads.
+template <int N>
+constexpr int units_per_block() { return kBlock / (N / kR); }
+
+// The field travels between the passes of a persistent march through global
+// memory while the kernel runs.  The L2 caches of the eight XCDs are not
+// coherent with each other, so every access to a buffer written inside the
+// kernel is an agent-scope relaxed atomic (a load that does not hit a stale
+// L2 line, a store that writes through to the device coherence point).
+// Read-only data (propagator, twiddles, dn, dL/dI) keeps ordinary cached
+// loads.
 __device__ __forceinline__ float2 ld_shared_field(const float2* p) {
     const unsigned long long v = __hip_atomic_load(reinterpret_cast<const unsigned long long*>(p),
                                                    __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
@@ -45,7 +59,8 @@ __device__ __forceinline__ void st_shared_field(float2* p, float2 v) {
 
 size_t plan_bytes(int nx, int ny) {
     return align_up(sizeof(float2) * (size_t)nx * ny) + align_up(sizeof(float2) * nx) +
-           align_up(sizeof(float2) * ny) + sizeof(unsigned) * kBarWords;
+           align_up(sizeof(float2) * ny) + align_up(sizeof(int) * nx) +
+           align_up(sizeof(int) * ny) + sizeof(unsigned) * kBarWords;
 }
 
 Plan plan_carve(void* ws, int nx, int ny) {
@@ -57,24 +72,32 @@ Plan plan_carve(void* ws, int nx, int ny) {
     b += align_up(sizeof(float2) * nx);
     p.twy = b;
     b += align_up(sizeof(float2) * ny);
+    p.permx = b;
+    b += align_up(sizeof(int) * nx);
+    p.permy = b;
+    b += align_up(sizeof(int) * ny);
     p.counter = b;
     return p;
 }
 
+// Fills the propagator in storage order (when with_h), both twiddle tables,
+// both storage-slot -> frequency tables, and zeroes the barrier words.
 __global__ void plan_kernel(float2* __restrict__ H, float2* __restrict__ twx,
-                            float2* __restrict__ twy, unsigned* __restrict__ counter, int nx,
-                            int ny, double dx, double dz, double lam, double n0) {
+                            float2* __restrict__ twy, int* __restrict__ permx,
+                            int* __restrict__ permy, unsigned* __restrict__ counter, int nx,
+                            int ny, double dx, double dz, double lam, double n0, int with_h) {
     if (blockIdx.x == 0)
         for (int i = threadIdx.x; i < kBarWords; i += blockDim.x) counter[i] = 0u;
     const double kPi = 3.14159265358979323846;
-    const long total = (long)nx * ny + nx + ny;
+    const long nh = with_h ? (long)nx * ny : 0;
+    const long total = nh + 2L * (nx + ny);
     const double k0 = 2.0 * kPi / lam, k = n0 * k0;
     const double thr_sqrt = (double)nx * (double)ny * n0 * dx / lam;
     const double thr = thr_sqrt * thr_sqrt;
     const double scale = 1.0 / ((double)nx * (double)ny);
     for (long e = blockIdx.x * (long)blockDim.x + threadIdx.x; e < total;
          e += (long)gridDim.x * blockDim.x) {
-        if (e < (long)nx * ny) {
+        if (e < nh) {
             const int py = (int)(e / nx), px = (int)(e % nx);
             // storage slot -> frequency index on each axis
             const int m = fft_freq_of_store(nx, kR, px);
@@ -91,24 +114,28 @@ __global__ void plan_kernel(float2* __restrict__ H, float2* __restrict__ twx,
                 h = make_float2((float)(cv * scale), (float)(sv * scale));
             }
             H[e] = h;
-        } else {
-            const long t = e - (long)nx * ny;
+        } else if (e < nh + nx + ny) {
+            const long t = e - nh;
             const int n = t < nx ? nx : ny;
             const long i = t < nx ? t : t - nx;
             double sv, cv;
             sincos(-2.0 * kPi * (double)i / n, &sv, &cv);
             (t < nx ? twx : twy)[i] = make_float2((float)cv, (float)sv);
+        } else {
+            const long t = e - nh - nx - ny;
+            if (t < nx) permx[t] = fft_freq_of_store(nx, kR, (int)t);
+            else permy[t - nx] = fft_freq_of_store(ny, kR, (int)(t - nx));
         }
     }
 }
 
-hipError_t launch_plan(const Geom& g, const Plan& p, hipStream_t s) {
-    const long total = (long)g.nx * g.ny + g.nx + g.ny;
+hipError_t launch_plan(const Geom& g, const Plan& p, bool with_h, hipStream_t s) {
+    const long total = (with_h ? (long)g.nx * g.ny : 0) + 2L * (g.nx + g.ny);
     const int threads = 256;
     const long blocks = (total + threads - 1) / threads;
     plan_kernel<<<(unsigned)(blocks < 4096 ? blocks : 4096), threads, 0, s>>>(
-        (float2*)p.H, (float2*)p.twx, (float2*)p.twy, (unsigned*)p.counter, g.nx, g.ny, g.dx,
-        g.dz, g.wavelength, g.n0);
+        (float2*)p.H, (float2*)p.twx, (float2*)p.twy, (int*)p.permx, (int*)p.permy,
+        (unsigned*)p.counter, g.nx, g.ny, g.dx, g.dz, g.wavelength, g.n0, with_h ? 1 : 0);
     return hipGetLastError();
 }
 
@@ -116,14 +143,8 @@ hipError_t launch_plan(const Geom& g, const Plan& p, hipStream_t s) {
 // pass bodies
 //
 // Every workgroup has 256 threads.  A row unit is B = 256 / (nx/16) rows, a
-// column unit W = 256 / (ny/16) columns; units past the field's edge idle but
-// still take part in the workgroup barriers.
-
-enum RowMode { kHead = 0, kMid = 1, kTail = 2 };
-constexpr int kBlock = 256;
-
-template <int N>
-constexpr int units_per_block() { return kBlock / (N / kR); }
+// column unit W = 256 / (ny/16) columns; units past the field's edge compute
+// on row / column 0, store nothing and still take part in the barriers.
 
 // workgroup-wide and wavefront-wide LDS ordering points
 struct BlockSync {
@@ -168,57 +189,106 @@ __device__ __forceinline__ void load_dn(float (&d)[kR], int unit, int ny,
     for (int i = 0; i < kR; ++i) d[i] = dn[rowoff + i * T + tau];
 }
 
-template <int NX, int MODE>
-__device__ __forceinline__ void row_unit(int unit, int ny, const float2* src, float2* dst,
-                                         const float (&d)[kR], float* __restrict__ inten,
-                                         const Twiddles<NX, kR>& twx, float k0dz,
+// What a row pass takes, does and leaves.
+enum RowIn : int { kSpecIn = 0, kNaturalIn = 1, kZeroIn = 2 };
+enum RowOps : int { kNoOps = 0, kScreen = 1, kAdjointOps = 2 };
+enum RowOut : int { kSpecOut = 0, kNaturalOut = 1, kNoOut = 2 };
+
+struct RowArgs {
+    const float2* src;  // spectrum (working buffer) or natural field
+    float2* dst;        // spectrum (working buffer) or natural field
+    float* inten;       // forward: I slice, or null
+    float2* keep;       // forward: copy of the natural u_{j+1}, or null
+    const float2* u;    // adjoint: natural u_{j+1}
+    const float* gI;    // adjoint: dL/dI slice, or null
+    float* gdn;         // adjoint: dL/ddn slice, or null
+    float k0dz;
+};
+
+template <int NX, int IN, int OPS, int OUT>
+__device__ __forceinline__ void row_unit(int unit, int ny, const RowArgs& a,
+                                         const float (&d)[kR], const Twiddles<NX, kR>& twx,
                                          float2* smem) {
     constexpr int T = NX / kR, B = units_per_block<NX>();
     const int sub = threadIdx.x / T, tau = threadIdx.x % T;
     const int row = unit * B + sub;
-    const bool on = row < ny;  // rows past the edge compute on row 0 and store nothing
+    const bool on = row < ny;
     const size_t rowoff = (size_t)(on ? row : 0) * NX;
     float2* lds = smem + sub * lds_size<NX>();
     const RowSync<NX> sync;
     float2 v[kR];
-    if constexpr (MODE == kHead) {
+    if constexpr (IN == kZeroIn) {
 #pragma unroll
-        for (int i = 0; i < kR; ++i) v[i] = src[rowoff + i * T + tau];
+        for (int i = 0; i < kR; ++i) v[i] = make_float2(0.f, 0.f);
+    } else if constexpr (IN == kNaturalIn) {
+#pragma unroll
+        for (int i = 0; i < kR; ++i) v[i] = ld_shared_field(a.src + rowoff + i * T + tau);
     } else {
 #pragma unroll
-        for (int r = 0; r < kR; ++r) v[r] = ld_shared_field(src + rowoff + r * T + tau);
+        for (int r = 0; r < kR; ++r) v[r] = ld_shared_field(a.src + rowoff + r * T + tau);
         fft_inverse<NX, kR, 1>(v, lds, tau, twx, sync);
+    }
+    if constexpr (OPS == kScreen) {
         float ph[kR];
 #pragma unroll
-        for (int i = 0; i < kR; ++i) ph[i] = k0dz * d[i];
+        for (int i = 0; i < kR; ++i) ph[i] = a.k0dz * d[i];
         apply_screen(v, ph);
-        if (inten && on) {
+        if (a.inten && on) {
 #pragma unroll
-            for (int i = 0; i < kR; ++i) inten[rowoff + i * T + tau] = c_abs2(v[i]);
+            for (int i = 0; i < kR; ++i) a.inten[rowoff + i * T + tau] = c_abs2(v[i]);
         }
+        if (a.keep && on) {
+#pragma unroll
+            for (int i = 0; i < kR; ++i) st_shared_field(a.keep + rowoff + i * T + tau, v[i]);
+        }
+    } else if constexpr (OPS == kAdjointOps) {
+        float2 u[kR];
+#pragma unroll
+        for (int i = 0; i < kR; ++i) u[i] = ld_shared_field(a.u + rowoff + i * T + tau);
+        if (a.gI) {
+#pragma unroll
+            for (int i = 0; i < kR; ++i) {
+                const float w = 2.f * a.gI[rowoff + i * T + tau];
+                v[i] = make_float2(fmaf(w, u[i].x, v[i].x), fmaf(w, u[i].y, v[i].y));
+            }
+        }
+        if (a.gdn && on) {
+#pragma unroll
+            for (int i = 0; i < kR; ++i)
+                a.gdn[rowoff + i * T + tau] = a.k0dz * fmaf(v[i].y, u[i].x, -v[i].x * u[i].y);
+        }
+        float ph[kR];
+#pragma unroll
+        for (int i = 0; i < kR; ++i) ph[i] = -a.k0dz * d[i];
+        apply_screen(v, ph);
     }
-    if constexpr (MODE == kTail) {
-        if (on) {
-#pragma unroll
-            for (int i = 0; i < kR; ++i) dst[rowoff + i * T + tau] = v[i];
-        }
-    } else {
+    if constexpr (OUT == kSpecOut) {
         fft_forward<NX, kR, 1>(v, lds, tau, twx, sync);
         if (on) {
 #pragma unroll
-            for (int r = 0; r < kR; ++r) st_shared_field(dst + rowoff + r * T + tau, v[r]);
+            for (int r = 0; r < kR; ++r) st_shared_field(a.dst + rowoff + r * T + tau, v[r]);
+        }
+    } else if constexpr (OUT == kNaturalOut) {
+        if (on) {
+#pragma unroll
+            for (int i = 0; i < kR; ++i) a.dst[rowoff + i * T + tau] = v[i];
         }
     }
 }
 
+// Column pass on a working buffer: forward column FFTs, x H (or conj(H)),
+// inverse column FFTs.  With spec_out, the multiplied spectrum is also written
+// to spec_out in natural DFT order (the pupil-plane gradient).
 template <int NY, bool CONJ>
 __device__ __forceinline__ void col_unit(int unit, int nx, float2* work,
                                          const float2* __restrict__ H,
-                                         const Twiddles<NY, kR>& twy, float2* smem) {
+                                         const Twiddles<NY, kR>& twy, float2* smem,
+                                         float2* spec_out, const int* __restrict__ permx,
+                                         const int* __restrict__ permy) {
     constexpr int T = NY / kR, W = units_per_block<NY>();
     const int w = threadIdx.x % W, t = threadIdx.x / W;
     const int c = unit * W + w;
-    const bool on = c < nx;  // columns past the edge compute on column 0 and store nothing
+    const bool on = c < nx;
     const size_t col = on ? (size_t)c : 0;
     float2* lds = smem + w;
     const BlockSync sync;
@@ -230,6 +300,11 @@ __device__ __forceinline__ void col_unit(int unit, int nx, float2* work,
     fft_forward<NY, kR, W>(v, lds, t, twy, sync);
 #pragma unroll
     for (int r = 0; r < kR; ++r) v[r] = CONJ ? c_mulc(v[r], h[r]) : c_mul(v[r], h[r]);
+    if (spec_out && on) {
+        const size_t m = (size_t)permx[col];
+#pragma unroll
+        for (int r = 0; r < kR; ++r) spec_out[(size_t)permy[r * T + t] * nx + m] = v[r];
+    }
     fft_inverse<NY, kR, W>(v, lds, t, twy, sync);
     if (on) {
 #pragma unroll
@@ -238,7 +313,7 @@ __device__ __forceinline__ void col_unit(int unit, int nx, float2* work,
 }
 
 // ---------------------------------------------------------------------------
-// grid barrier of the persistent march
+// grid barrier of the persistent marches
 //
 // Two levels, no cache maintenance.  Workgroup b belongs to group b % 8 (the
 // XCD the hardware deals it to).  Each arrival bumps its group's counter; the
@@ -246,8 +321,8 @@ __device__ __forceinline__ void col_unit(int unit, int nx, float2* work,
 // publishes the barrier's generation to eight per-group flags, which the
 // groups poll.  Every counter and flag sits in its own 128-byte line.  All of
 // a wave's stores are complete (s_waitcnt) before its workgroup arrives, and
-// the shared field is only accessed with agent-coherent operations, so no L2
-// write-back or invalidation is needed.
+// buffers written inside the kernel are only accessed with agent-coherent
+// operations, so no L2 write-back or invalidation is needed.
 //
 // Every workgroup is resident (cooperative launch), so the wait ends; as a
 // guard against a launch that is not, the spin is bounded and a time-out is
@@ -291,6 +366,17 @@ __device__ __forceinline__ void grid_sync(unsigned* bar, unsigned gen, bool& abo
     __syncthreads();
 }
 
+// XCD-aware unit order: workgroups are dealt round-robin over the 8 XCDs, so
+// give each XCD a contiguous range of units (neighbouring columns share cache
+// lines).
+__device__ __forceinline__ int virtual_block() {
+    const int G = gridDim.x, b = blockIdx.x;
+    return (G % 8 == 0) ? (b % 8) * (G / 8) + b / 8 : b;
+}
+
+// ---------------------------------------------------------------------------
+// persistent forward march
+
 struct MarchArgs {
     const float2* field_in;
     float2* work;
@@ -307,11 +393,7 @@ struct MarchArgs {
 template <int NX, int NY>
 __global__ __launch_bounds__(kBlock) void march_kernel(MarchArgs a) {
     extern __shared__ float2 smem[];
-    const int G = gridDim.x, b = blockIdx.x;
-    // XCD-aware order: workgroups are dealt round-robin over the 8 XCDs, so
-    // give each XCD a contiguous range of units (neighbouring columns share
-    // cache lines)
-    const int v = (G % 8 == 0) ? (b % 8) * (G / 8) + b / 8 : b;
+    const int G = gridDim.x, v = virtual_block();
     const int rows_u = (a.ny + units_per_block<NX>() - 1) / units_per_block<NX>();
     const int cols_u = (a.nx + units_per_block<NY>() - 1) / units_per_block<NY>();
     const size_t plane = (size_t)a.nx * a.ny;
@@ -323,24 +405,250 @@ __global__ __launch_bounds__(kBlock) void march_kernel(MarchArgs a) {
     twy.load(a.twy, threadIdx.x / units_per_block<NY>());
     float d[kR];
     for (int i = 0; i < kR; ++i) d[i] = 0.f;
+    RowArgs ra{a.field_in, a.work, nullptr, nullptr, nullptr, nullptr, nullptr, a.k0dz};
     for (int u = v; u < rows_u; u += G)
-        row_unit<NX, kHead>(u, a.ny, a.field_in, a.work, d, nullptr, twx, a.k0dz, smem);
+        row_unit<NX, kNaturalIn, kNoOps, kSpecOut>(u, a.ny, ra, d, twx, smem);
+    ra.src = a.work;
     // a workgroup with a single row unit fetches its dn slice during the column pass
     const bool one_row_unit = rows_u <= G;
     for (int j = 0; j < a.steps; ++j) {
         const float* dnj = a.dn + j * plane;
-        float* ij = a.inten ? a.inten + j * plane : nullptr;
+        ra.inten = a.inten ? a.inten + j * plane : nullptr;
         if (one_row_unit) load_dn<NX>(d, v < rows_u ? v : 0, a.ny, dnj);
         grid_sync(a.counter, ++nbar, abort);
-        for (int u = v; u < cols_u; u += G) col_unit<NY, false>(u, a.nx, a.work, a.H, twy, smem);
+        for (int u = v; u < cols_u; u += G)
+            col_unit<NY, false>(u, a.nx, a.work, a.H, twy, smem, nullptr, nullptr, nullptr);
         grid_sync(a.counter, ++nbar, abort);
         for (int u = v; u < rows_u; u += G) {
             if (!one_row_unit) load_dn<NX>(d, u, a.ny, dnj);
             if (j + 1 < a.steps)
-                row_unit<NX, kMid>(u, a.ny, a.work, a.work, d, ij, twx, a.k0dz, smem);
+                row_unit<NX, kSpecIn, kScreen, kSpecOut>(u, a.ny, ra, d, twx, smem);
             else
-                row_unit<NX, kTail>(u, a.ny, a.work, a.work, d, ij, twx, a.k0dz, smem);
+                row_unit<NX, kSpecIn, kScreen, kNaturalOut>(u, a.ny, ra, d, twx, smem);
         }
+    }
+}
+
+// ---------------------------------------------------------------------------
+// persistent adjoint march with checkpointing
+//
+//   1. forward march from u_0 keeping u at every K-th slice boundary;
+//   2. for each segment of K steps, last to first: recompute the segment's
+//      fields from its checkpoint (kept in `seg`), then run its adjoint steps
+//      backwards; the adjoint state crosses segments in `gwork`;
+//   3. a tail row pass brings g_0 back to natural order.
+// Memory: (ceil(N/K) + K + 2) fields; compute: about three forward marches.
+
+struct AdjointArgs {
+    const float2* field_in;
+    const float* dn;
+    const float2* gout;  // dL/du_N or null
+    const float* gI;     // dL/dI or null
+    float2* gin;         // dL/du_0 or null
+    float2* gspec;       // dL/dU_0 or null
+    float* gdn;          // dL/ddn or null
+    float2* fwork;
+    float2* gwork;
+    float2* ckpt;  // [ceil(N/K)] fields (slot 0 unused: u_0 is field_in)
+    float2* seg;   // [K] fields
+    const float2* H;
+    const float2* twx;
+    const float2* twy;
+    const int* permx;
+    const int* permy;
+    unsigned* counter;
+    int nx, ny, steps, K;
+    float k0dz;
+};
+
+template <int NX, int NY>
+__global__ __launch_bounds__(kBlock) void adjoint_kernel(AdjointArgs a) {
+    extern __shared__ float2 smem[];
+    const int G = gridDim.x, v = virtual_block();
+    const int rows_u = (a.ny + units_per_block<NX>() - 1) / units_per_block<NX>();
+    const int cols_u = (a.nx + units_per_block<NY>() - 1) / units_per_block<NY>();
+    const size_t plane = (size_t)a.nx * a.ny;
+    const int N = a.steps, K = a.K, C = (N + K - 1) / K;
+    unsigned nbar = 0;
+    bool abort = false;
+    Twiddles<NX, kR> twx;
+    Twiddles<NY, kR> twy;
+    twx.load(a.twx, threadIdx.x % (NX / kR));
+    twy.load(a.twy, threadIdx.x / units_per_block<NY>());
+    float d[kR];
+    for (int i = 0; i < kR; ++i) d[i] = 0.f;
+
+    auto col_pass = [&](float2* work, bool conj, float2* spec_out) {
+        for (int u = v; u < cols_u; u += G) {
+            if (conj)
+                col_unit<NY, true>(u, a.nx, work, a.H, twy, smem, spec_out, a.permx, a.permy);
+            else
+                col_unit<NY, false>(u, a.nx, work, a.H, twy, smem, nullptr, nullptr, nullptr);
+        }
+    };
+
+    // 1. checkpoints u_K, u_2K, ..., u_(C-1)K
+    if (C > 1) {
+        RowArgs ra{a.field_in, a.fwork, nullptr, nullptr, nullptr, nullptr, nullptr, a.k0dz};
+        for (int u = v; u < rows_u; u += G)
+            row_unit<NX, kNaturalIn, kNoOps, kSpecOut>(u, a.ny, ra, d, twx, smem);
+        ra.src = a.fwork;
+        const int last = (C - 1) * K;
+        for (int j = 0; j < last; ++j) {
+            grid_sync(a.counter, ++nbar, abort);
+            col_pass(a.fwork, false, nullptr);
+            grid_sync(a.counter, ++nbar, abort);
+            ra.keep = ((j + 1) % K == 0) ? a.ckpt + (size_t)((j + 1) / K) * plane : nullptr;
+            for (int u = v; u < rows_u; u += G) {
+                load_dn<NX>(d, u, a.ny, a.dn + j * plane);
+                if (j + 1 < last)
+                    row_unit<NX, kSpecIn, kScreen, kSpecOut>(u, a.ny, ra, d, twx, smem);
+                else
+                    row_unit<NX, kSpecIn, kScreen, kNoOut>(u, a.ny, ra, d, twx, smem);
+            }
+        }
+    }
+
+    // 2. segments, last to first
+    for (int c = C - 1; c >= 0; --c) {
+        const int start = c * K, L = (N - start) < K ? (N - start) : K;
+        grid_sync(a.counter, ++nbar, abort);
+        RowArgs fr{c == 0 ? a.field_in : a.ckpt + (size_t)c * plane, a.fwork, nullptr, nullptr,
+                   nullptr, nullptr, nullptr, a.k0dz};
+        for (int u = v; u < rows_u; u += G)
+            row_unit<NX, kNaturalIn, kNoOps, kSpecOut>(u, a.ny, fr, d, twx, smem);
+        fr.src = a.fwork;
+        for (int s = 0; s < L; ++s) {
+            grid_sync(a.counter, ++nbar, abort);
+            col_pass(a.fwork, false, nullptr);
+            grid_sync(a.counter, ++nbar, abort);
+            fr.keep = a.seg + (size_t)s * plane;
+            for (int u = v; u < rows_u; u += G) {
+                load_dn<NX>(d, u, a.ny, a.dn + (start + s) * plane);
+                if (s + 1 < L)
+                    row_unit<NX, kSpecIn, kScreen, kSpecOut>(u, a.ny, fr, d, twx, smem);
+                else
+                    row_unit<NX, kSpecIn, kScreen, kNoOut>(u, a.ny, fr, d, twx, smem);
+            }
+        }
+        for (int s = L - 1; s >= 0; --s) {
+            const int j = start + s;
+            RowArgs br{a.gwork, a.gwork, nullptr, nullptr, a.seg + (size_t)s * plane,
+                       a.gI ? a.gI + j * plane : nullptr, a.gdn ? a.gdn + j * plane : nullptr,
+                       a.k0dz};
+            grid_sync(a.counter, ++nbar, abort);
+            for (int u = v; u < rows_u; u += G) {
+                load_dn<NX>(d, u, a.ny, a.dn + j * plane);
+                if (j + 1 < N) {
+                    row_unit<NX, kSpecIn, kAdjointOps, kSpecOut>(u, a.ny, br, d, twx, smem);
+                } else if (a.gout) {
+                    br.src = a.gout;
+                    row_unit<NX, kNaturalIn, kAdjointOps, kSpecOut>(u, a.ny, br, d, twx, smem);
+                } else {
+                    row_unit<NX, kZeroIn, kAdjointOps, kSpecOut>(u, a.ny, br, d, twx, smem);
+                }
+            }
+            grid_sync(a.counter, ++nbar, abort);
+            col_pass(a.gwork, true, j == 0 ? a.gspec : nullptr);
+        }
+    }
+
+    // 3. g_0 in natural order
+    if (a.gin) {
+        grid_sync(a.counter, ++nbar, abort);
+        RowArgs tr{a.gwork, a.gin, nullptr, nullptr, nullptr, nullptr, nullptr, a.k0dz};
+        for (int u = v; u < rows_u; u += G)
+            row_unit<NX, kSpecIn, kNoOps, kNaturalOut>(u, a.ny, tr, d, twx, smem);
+    }
+}
+
+// ---------------------------------------------------------------------------
+// natural-order 2-D FFT (unnormalised; the inverse uses conj(DFT(conj x)))
+
+template <int NY>
+__global__ __launch_bounds__(kBlock) void fft2_cols_kernel(const float2* in, float2* out, int nx,
+                                                           const float2* __restrict__ tw,
+                                                           const int* __restrict__ permy,
+                                                           int inverse, float scale) {
+    constexpr int T = NY / kR, W = units_per_block<NY>();
+    extern __shared__ float2 smem[];
+    const int w = threadIdx.x % W, t = threadIdx.x / W;
+    const int c = blockIdx.x * W + w;
+    const bool on = c < nx;
+    const size_t col = on ? (size_t)c : 0;
+    Twiddles<NY, kR> twy;
+    twy.load(tw, t);
+    float2 v[kR];
+    const float sg = inverse ? -1.f : 1.f;
+#pragma unroll
+    for (int i = 0; i < kR; ++i) {
+        const float2 x = in[(size_t)(i * T + t) * nx + col];
+        v[i] = make_float2(x.x, sg * x.y);
+    }
+    fft_forward<NY, kR, W>(v, smem + w, t, twy, BlockSync());
+    __syncthreads();  // every load of an in-place call precedes every store
+    if (on) {
+#pragma unroll
+        for (int r = 0; r < kR; ++r)
+            out[(size_t)permy[r * T + t] * nx + col] =
+                make_float2(scale * v[r].x, sg * scale * v[r].y);
+    }
+}
+
+template <int NX>
+__global__ __launch_bounds__(kBlock) void fft2_rows_kernel(float2* io, int ny,
+                                                           const float2* __restrict__ tw,
+                                                           const int* __restrict__ permx,
+                                                           int inverse) {
+    constexpr int T = NX / kR, B = units_per_block<NX>();
+    extern __shared__ float2 smem[];
+    const int sub = threadIdx.x / T, tau = threadIdx.x % T;
+    const int row = blockIdx.x * B + sub;
+    const bool on = row < ny;
+    const size_t rowoff = (size_t)(on ? row : 0) * NX;
+    Twiddles<NX, kR> twx;
+    twx.load(tw, tau);
+    float2 v[kR];
+    const float sg = inverse ? -1.f : 1.f;
+#pragma unroll
+    for (int i = 0; i < kR; ++i) {
+        const float2 x = io[rowoff + i * T + tau];
+        v[i] = make_float2(x.x, sg * x.y);
+    }
+    fft_forward<NX, kR, 1>(v, smem + sub * lds_size<NX>(), tau, twx, BlockSync());
+    __syncthreads();  // every load of the row precedes every store
+    if (on) {
+#pragma unroll
+        for (int r = 0; r < kR; ++r) io[rowoff + permx[r * T + tau]] = make_float2(v[r].x, sg * v[r].y);
+    }
+}
+
+// ---------------------------------------------------------------------------
+// pupil plane: U0 = A exp(i phi) exp(-i kz z_f), and dL/dphi = Im(dL/dU0 conj(U0))
+
+__global__ void pupil_spectrum_kernel(const float* __restrict__ amp,
+                                      const float* __restrict__ phase, int nx, int ny, double dx,
+                                      double k, double z_f, float2* __restrict__ U) {
+    const double kPi = 3.14159265358979323846;
+    const long n = (long)nx * ny;
+    for (long e = blockIdx.x * (long)blockDim.x + threadIdx.x; e < n;
+         e += (long)gridDim.x * blockDim.x) {
+        const int l = (int)(e / nx), m = (int)(e % nx);
+        const double kx = 2.0 * kPi * (double)(m < nx / 2 ? m : m - nx) / (nx * dx);
+        const double ky = 2.0 * kPi * (double)(l < ny / 2 ? l : l - ny) / (ny * dx);
+        const double kz = sqrt(fmax(k * k - kx * kx - ky * ky, 0.0));
+        double sv, cv;
+        sincos((double)phase[e] - kz * z_f, &sv, &cv);
+        U[e] = make_float2((float)(amp[e] * cv), (float)(amp[e] * sv));
+    }
+}
+
+__global__ void pupil_grad_kernel(const float2* __restrict__ G, const float2* __restrict__ U,
+                                  long n, float* __restrict__ gphi) {
+    for (long e = blockIdx.x * (long)blockDim.x + threadIdx.x; e < n;
+         e += (long)gridDim.x * blockDim.x) {
+        const float2 g = G[e], u = U[e];
+        gphi[e] = fmaf(g.y, u.x, -g.x * u.y);
     }
 }
 
@@ -359,46 +667,50 @@ static int device_cus() {
 }
 
 template <int NX, int NY>
-static hipError_t launch_march_n(MarchArgs a, hipStream_t s) {
-    constexpr int BX = units_per_block<NX>(), WY = units_per_block<NY>();
-    const int rows_u = (a.ny + BX - 1) / BX, cols_u = (a.nx + WY - 1) / WY;
+static size_t persistent_lds() {
+    const size_t lds_r = sizeof(float2) * units_per_block<NX>() * lds_size<NX>();
+    const size_t lds_c = sizeof(float2) * units_per_block<NY>() * lds_size<NY>();
+    return lds_r > lds_c ? lds_r : lds_c;
+}
+
+template <int NX, int NY>
+static int persistent_grid(int nx, int ny) {
+    const int rows_u = (ny + units_per_block<NX>() - 1) / units_per_block<NX>();
+    const int cols_u = (nx + units_per_block<NY>() - 1) / units_per_block<NY>();
     const int cus = device_cus();
-    if (cus <= 0) return hipErrorNoDevice;
     int grid = rows_u > cols_u ? rows_u : cols_u;
-    if (grid > cus) grid = cus;
-    const size_t lds_r = sizeof(float2) * BX * lds_size<NX>();
-    const size_t lds_c = sizeof(float2) * WY * lds_size<NY>();
-    const size_t lds = lds_r > lds_c ? lds_r : lds_c;
-    void* args[] = {&a};
-    return hipLaunchCooperativeKernel(reinterpret_cast<const void*>(&march_kernel<NX, NY>),
-                                      dim3(grid), dim3(kBlock), args, (unsigned)lds, s);
+    return grid > cus ? cus : grid;
 }
 
-template <int NX>
-static hipError_t launch_march_x(MarchArgs a, hipStream_t s) {
-    switch (a.ny) {
-        case 32: return launch_march_n<NX, 32>(a, s);
-        case 64: return launch_march_n<NX, 64>(a, s);
-        case 128: return launch_march_n<NX, 128>(a, s);
-        case 256: return launch_march_n<NX, 256>(a, s);
-        case 512: return launch_march_n<NX, 512>(a, s);
-        case 1024: return launch_march_n<NX, 1024>(a, s);
-        case 2048: return launch_march_n<NX, 2048>(a, s);
+template <typename F>
+static hipError_t dispatch2(int nx, int ny, F&& f) {
+    auto by_y = [&](auto xc) -> hipError_t {
+        constexpr int X = decltype(xc)::value;
+        switch (ny) {
+            case 32: return f(std::integral_constant<int, X>{}, std::integral_constant<int, 32>{});
+            case 64: return f(std::integral_constant<int, X>{}, std::integral_constant<int, 64>{});
+            case 128: return f(std::integral_constant<int, X>{}, std::integral_constant<int, 128>{});
+            case 256: return f(std::integral_constant<int, X>{}, std::integral_constant<int, 256>{});
+            case 512: return f(std::integral_constant<int, X>{}, std::integral_constant<int, 512>{});
+            case 1024: return f(std::integral_constant<int, X>{}, std::integral_constant<int, 1024>{});
+            case 2048: return f(std::integral_constant<int, X>{}, std::integral_constant<int, 2048>{});
+            default: return hipErrorInvalidValue;
+        }
+    };
+    switch (nx) {
+        case 32: return by_y(std::integral_constant<int, 32>{});
+        case 64: return by_y(std::integral_constant<int, 64>{});
+        case 128: return by_y(std::integral_constant<int, 128>{});
+        case 256: return by_y(std::integral_constant<int, 256>{});
+        case 512: return by_y(std::integral_constant<int, 512>{});
+        case 1024: return by_y(std::integral_constant<int, 1024>{});
+        case 2048: return by_y(std::integral_constant<int, 2048>{});
         default: return hipErrorInvalidValue;
     }
 }
 
-static hipError_t launch_march(MarchArgs a, hipStream_t s) {
-    switch (a.nx) {
-        case 32: return launch_march_x<32>(a, s);
-        case 64: return launch_march_x<64>(a, s);
-        case 128: return launch_march_x<128>(a, s);
-        case 256: return launch_march_x<256>(a, s);
-        case 512: return launch_march_x<512>(a, s);
-        case 1024: return launch_march_x<1024>(a, s);
-        case 2048: return launch_march_x<2048>(a, s);
-        default: return hipErrorInvalidValue;
-    }
+static float k0dz_of(const Geom& g) {
+    return (float)(2.0 * 3.14159265358979323846 / g.wavelength * g.dz);
 }
 
 hipError_t launch_forward(const Geom& g, const Plan& p, const MarchIO& io, hipStream_t s) {
@@ -409,20 +721,76 @@ hipError_t launch_forward(const Geom& g, const Plan& p, const MarchIO& io, hipSt
                                   hipMemcpyDeviceToDevice, s);
         return hipSuccess;
     }
-    MarchArgs a;
-    a.field_in = (const float2*)io.field_in;
-    a.work = (float2*)io.field_out;
-    a.dn = io.dn;
-    a.inten = io.intensity;
-    a.H = (const float2*)p.H;
-    a.twx = (const float2*)p.twx;
-    a.twy = (const float2*)p.twy;
-    a.counter = (unsigned*)p.counter;
-    a.nx = g.nx;
-    a.ny = g.ny;
-    a.steps = g.steps;
-    a.k0dz = (float)(2.0 * 3.14159265358979323846 / g.wavelength * g.dz);
-    return launch_march(a, s);
+    if (device_cus() <= 0) return hipErrorNoDevice;
+    MarchArgs a{(const float2*)io.field_in, (float2*)io.field_out, io.dn, io.intensity,
+                (const float2*)p.H, (const float2*)p.twx, (const float2*)p.twy,
+                (unsigned*)p.counter, g.nx, g.ny, g.steps, k0dz_of(g)};
+    return dispatch2(g.nx, g.ny, [&](auto xc, auto yc) {
+        constexpr int NX = decltype(xc)::value, NY = decltype(yc)::value;
+        void* args[] = {&a};
+        return hipLaunchCooperativeKernel(reinterpret_cast<const void*>(&march_kernel<NX, NY>),
+                                          dim3(persistent_grid<NX, NY>(g.nx, g.ny)),
+                                          dim3(kBlock), args, (unsigned)persistent_lds<NX, NY>(),
+                                          s);
+    });
+}
+
+size_t adjoint_fields(int steps, int K) {
+    const int C = (steps + K - 1) / K;
+    return (size_t)C + K + 2;
+}
+
+hipError_t launch_adjoint(const Geom& g, const Plan& p, const AdjointIO& io, int K, void* fields,
+                          hipStream_t s) {
+    const size_t plane = (size_t)g.nx * g.ny;
+    if (device_cus() <= 0) return hipErrorNoDevice;
+    float2* f = (float2*)fields;
+    const int C = (g.steps + K - 1) / K;
+    AdjointArgs a{(const float2*)io.field_in, io.dn, (const float2*)io.grad_out, io.grad_inten,
+                  (float2*)io.grad_in, (float2*)io.grad_spec, io.grad_dn, f, f + plane,
+                  f + 2 * plane, f + (2 + (size_t)C) * plane,
+                  (const float2*)p.H, (const float2*)p.twx, (const float2*)p.twy,
+                  (const int*)p.permx, (const int*)p.permy, (unsigned*)p.counter, g.nx, g.ny,
+                  g.steps, K, k0dz_of(g)};
+    return dispatch2(g.nx, g.ny, [&](auto xc, auto yc) {
+        constexpr int NX = decltype(xc)::value, NY = decltype(yc)::value;
+        void* args[] = {&a};
+        return hipLaunchCooperativeKernel(reinterpret_cast<const void*>(&adjoint_kernel<NX, NY>),
+                                          dim3(persistent_grid<NX, NY>(g.nx, g.ny)),
+                                          dim3(kBlock), args, (unsigned)persistent_lds<NX, NY>(),
+                                          s);
+    });
+}
+
+hipError_t launch_fft2(const void* in, void* out, int nx, int ny, bool inverse, float scale,
+                       const Plan& p, hipStream_t s) {
+    return dispatch2(nx, ny, [&](auto xc, auto yc) {
+        constexpr int NX = decltype(xc)::value, NY = decltype(yc)::value;
+        constexpr int W = units_per_block<NY>(), B = units_per_block<NX>();
+        fft2_cols_kernel<NY><<<(nx + W - 1) / W, kBlock, sizeof(float2) * W * lds_size<NY>(), s>>>(
+            (const float2*)in, (float2*)out, nx, (const float2*)p.twy, (const int*)p.permy,
+            inverse ? 1 : 0, scale);
+        fft2_rows_kernel<NX><<<(ny + B - 1) / B, kBlock, sizeof(float2) * B * lds_size<NX>(), s>>>(
+            (float2*)out, ny, (const float2*)p.twx, (const int*)p.permx, inverse ? 1 : 0);
+        return hipGetLastError();
+    });
+}
+
+hipError_t launch_pupil_spectrum(const float* amp, const float* phase, const Geom& g, double z_f,
+                                 void* U, hipStream_t s) {
+    const long n = (long)g.nx * g.ny;
+    const long blocks = (n + 255) / 256;
+    const double k = 2.0 * 3.14159265358979323846 / g.wavelength * g.n0;
+    pupil_spectrum_kernel<<<(unsigned)(blocks < 4096 ? blocks : 4096), 256, 0, s>>>(
+        amp, phase, g.nx, g.ny, g.dx, k, z_f, (float2*)U);
+    return hipGetLastError();
+}
+
+hipError_t launch_pupil_grad(const void* G, const void* U, long n, float* gphi, hipStream_t s) {
+    const long blocks = (n + 255) / 256;
+    pupil_grad_kernel<<<(unsigned)(blocks < 4096 ? blocks : 4096), 256, 0, s>>>(
+        (const float2*)G, (const float2*)U, n, gphi);
+    return hipGetLastError();
 }
 
 }  // namespace bpm
