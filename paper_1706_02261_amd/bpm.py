@@ -213,3 +213,46 @@ class PupilBPMFunction(torch.autograd.Function):
                                 want_dn=ctx.needs_input_grad[2], checkpoint_every=ck)
         gphi = pupil_phase_grad(gspec, spec) if ctx.needs_input_grad[0] else None
         return gphi, None, gdn, None, None, None, None, None, None
+
+
+def propagate_batch(jobs, ws: torch.Tensor | None = None, stream=None):
+    """Run an uneven batch of marches in one persistent launch.
+
+    ``jobs``: sequence of dicts with keys field, dn, dx, dz, wavelength, n0 and
+    optional out, intensity (bool, default True), intensity_out.  Returns a
+    list of (field_out, intensity) per job."""
+    if len(jobs) == 0:
+        return []
+    arr = (_lib.Job * len(jobs))()
+    results = []
+    dev = None
+    for i, j in enumerate(jobs):
+        f, d = j["field"], j["dn"]
+        _need(f, f"jobs[{i}].field", torch.complex64)
+        _need(d, f"jobs[{i}].dn", torch.float32)
+        ny, nx = f.shape
+        if d.dim() != 3 or tuple(d.shape[1:]) != (ny, nx):
+            raise ValueError(f"jobs[{i}].dn has shape {tuple(d.shape)}, expected [steps][{ny}][{nx}]")
+        steps = d.shape[0]
+        out = j.get("out")
+        if out is None:
+            out = torch.empty_like(f)
+        _need(out, f"jobs[{i}].out", torch.complex64, (ny, nx))
+        inten = j.get("intensity_out")
+        if inten is None and j.get("intensity", True):
+            inten = torch.empty((steps, ny, nx), dtype=torch.float32, device=f.device)
+        if inten is not None:
+            _need(inten, f"jobs[{i}].intensity_out", torch.float32, (steps, ny, nx))
+        arr[i] = _lib.Job(f.data_ptr(), d.data_ptr(), nx, ny, steps, float(j["dx"]),
+                          float(j["dz"]), float(j["wavelength"]), float(j["n0"]),
+                          out.data_ptr(), 0 if inten is None else inten.data_ptr())
+        results.append((out, inten))
+        dev = f.device
+    need = lib().bpm_batch_workspace_size(arr, len(jobs))
+    if need == 0:
+        raise _lib.BpmError(_lib.BPM_ERR_UNSUPPORTED_SIZE, "unsupported job in batch")
+    if ws is None:
+        ws = workspace(need, dev)
+    rc = lib().bpm_propagate_batch(arr, len(jobs), _ptr(ws), ws.numel(), _stream_ptr(stream))
+    check(rc, "bpm_propagate_batch")
+    return results

@@ -5,7 +5,11 @@
 #include <cstdarg>
 #include <cstdint>
 #include <cstdio>
+#include <algorithm>
+#include <cstring>
+#include <mutex>
 #include <string>
+#include <vector>
 
 #include "../../include/bpm.h"
 #include "internal.hpp"
@@ -110,16 +114,166 @@ int bpm_propagate(const bpm_c64* field_in, const float* dn, int nx, int ny, int 
     return device_status(bpm::launch_forward(g, p, io, s), "forward march");
 }
 
+// ---------------------------------------------------------------------------
+// uneven batch
+
+}  // extern "C"
+
+namespace {
+
+// Host-side layout of a batch workspace: per-job plans, then the job table,
+// the segment table and the queue words.
+struct BatchLayout {
+    std::vector<size_t> plan_off;
+    size_t jobs_off, segs_off, q_off, total;
+    int n_segs, n_items;
+};
+
+int batch_passes(const bpm_job& j) { return j.steps > 0 ? 2 * j.steps + 1 : 0; }
+
+BatchLayout batch_layout(const bpm_job* jobs, int n) {
+    BatchLayout L;
+    size_t off = 0;
+    L.n_segs = 0;
+    L.n_items = 0;
+    for (int i = 0; i < n; ++i) {
+        L.plan_off.push_back(off);
+        off += bpm::align_up(bpm::plan_bytes(jobs[i].nx, jobs[i].ny));
+        const int P = batch_passes(jobs[i]);
+        L.n_segs += P;
+        const long items = jobs[i].steps > 0
+            ? (long)bpm::row_units(jobs[i].nx, jobs[i].ny) * (jobs[i].steps + 1) +
+              (long)bpm::col_units(jobs[i].nx, jobs[i].ny) * jobs[i].steps
+            : 0;
+        L.n_items += (int)items;
+    }
+    L.jobs_off = off;
+    off += bpm::align_up(sizeof(bpm::BatchJob) * (size_t)n);
+    L.segs_off = off;
+    off += bpm::align_up(sizeof(bpm::BatchSeg) * (size_t)L.n_segs);
+    L.q_off = off;
+    off += bpm::align_up(sizeof(unsigned) * (size_t)bpm::batch_queue_words(n));
+    L.total = off;
+    return L;
+}
+
+int check_batch(const bpm_job* jobs, int n) {
+    if (!jobs || n < 1) return fail(BPM_ERR_INVALID_ARG, "jobs must be a host array of n_jobs >= 1");
+    long items = 0;
+    for (int i = 0; i < n; ++i) {
+        const bpm_job& j = jobs[i];
+        int rc = check_geom(j.nx, j.ny, j.steps, j.dx, j.dz, j.wavelength, j.n0);
+        if (rc) return fail(rc, "job %d: %s", i, g_last_error.c_str());
+        if ((rc = check_field_ptrs(j.field_in, j.dn, j.steps, j.field_out)))
+            return fail(rc, "job %d: %s", i, g_last_error.c_str());
+        if (j.intensity_out && !aligned(j.intensity_out, 4))
+            return fail(BPM_ERR_INVALID_ARG, "job %d: intensity_out must be 4-byte aligned", i);
+        if (j.steps > 0)
+            items += (long)bpm::row_units(j.nx, j.ny) * (j.steps + 1) +
+                     (long)bpm::col_units(j.nx, j.ny) * j.steps;
+    }
+    if (items >= (1L << 31)) return fail(BPM_ERR_INVALID_ARG, "batch has too many work items");
+    return BPM_OK;
+}
+
+// Pinned staging for the job and segment tables; reused once the previous
+// upload has completed.
+std::mutex g_stage_mu;
+void* g_stage = nullptr;
+size_t g_stage_bytes = 0;
+hipEvent_t g_stage_done = nullptr;
+
+}  // namespace
+
+extern "C" {
+
 size_t bpm_batch_workspace_size(const bpm_job* jobs, int n_jobs) {
-    (void)jobs;
-    (void)n_jobs;
-    return 0;
+    if (!jobs || n_jobs < 1) return 0;
+    for (int i = 0; i < n_jobs; ++i)
+        if (!pow2_in_range(jobs[i].nx) || !pow2_in_range(jobs[i].ny) || jobs[i].steps < 0) return 0;
+    return batch_layout(jobs, n_jobs).total;
 }
 
 int bpm_propagate_batch(const bpm_job* jobs, int n_jobs, void* workspace,
                         size_t workspace_bytes, void* hip_stream) {
-    (void)jobs; (void)n_jobs; (void)workspace; (void)workspace_bytes; (void)hip_stream;
-    return fail(BPM_ERR_INVALID_ARG, "bpm_propagate_batch: not built yet");
+    int rc = check_batch(jobs, n_jobs);
+    if (rc) return rc;
+    const BatchLayout L = batch_layout(jobs, n_jobs);
+    if ((rc = check_workspace(workspace, workspace_bytes, L.total))) return rc;
+    hipStream_t s = static_cast<hipStream_t>(hip_stream);
+    char* ws = static_cast<char*>(workspace);
+
+    // job table, plans
+    std::vector<bpm::BatchJob> dj(n_jobs);
+    for (int i = 0; i < n_jobs; ++i) {
+        const bpm_job& j = jobs[i];
+        const bpm::Plan p = bpm::plan_carve(ws + L.plan_off[i], j.nx, j.ny);
+        dj[i] = bpm::BatchJob{j.field_in, j.dn, j.field_out, j.intensity_out, p.H, p.twx, p.twy,
+                              j.nx, j.ny, j.steps,
+                              (float)(2.0 * 3.14159265358979323846 / j.wavelength * j.dz)};
+        if (j.steps > 0) {
+            const bpm::Geom g{j.nx, j.ny, j.steps, j.dx, j.dz, j.wavelength, j.n0};
+            if ((rc = device_status(bpm::launch_plan(g, p, true, s), "batch plan"))) return rc;
+        } else if ((const void*)j.field_out != (const void*)j.field_in) {
+            hipError_t e = hipMemcpyAsync(j.field_out, j.field_in,
+                                          sizeof(bpm_c64) * (size_t)j.nx * j.ny,
+                                          hipMemcpyDeviceToDevice, s);
+            if ((rc = device_status(e, "batch copy"))) return rc;
+        }
+    }
+    // segment table: round r holds pass r of every job that has it, jobs of
+    // equal pass size side by side
+    std::vector<int> order(n_jobs);
+    for (int i = 0; i < n_jobs; ++i) order[i] = i;
+    std::stable_sort(order.begin(), order.end(), [&](int a, int b) {
+        return jobs[a].nx != jobs[b].nx ? jobs[a].nx < jobs[b].nx : jobs[a].ny < jobs[b].ny;
+    });
+    int maxP = 0;
+    for (int i = 0; i < n_jobs; ++i) maxP = std::max(maxP, batch_passes(jobs[i]));
+    std::vector<bpm::BatchSeg> segs;
+    segs.reserve(L.n_segs);
+    int first = 0;
+    for (int r = 0; r < maxP; ++r) {
+        for (int i : order) {
+            if (r >= batch_passes(jobs[i])) continue;
+            const int R = bpm::row_units(jobs[i].nx, jobs[i].ny);
+            const int C = bpm::col_units(jobs[i].nx, jobs[i].ny);
+            const int count = (r % 2 == 0) ? R : C;
+            const int need = r == 0 ? 0 : R + (r / 2) * C + ((r - 1) / 2) * R;
+            segs.push_back(bpm::BatchSeg{i, r, first, count, need});
+            first += count;
+        }
+    }
+    // upload both tables through pinned staging
+    {
+        std::lock_guard<std::mutex> lk(g_stage_mu);
+        const size_t jb = sizeof(bpm::BatchJob) * dj.size();
+        const size_t sb = sizeof(bpm::BatchSeg) * segs.size();
+        hipError_t e = hipSuccess;
+        if (g_stage_done) e = hipEventSynchronize(g_stage_done);
+        if (e == hipSuccess && g_stage_bytes < jb + sb) {
+            if (g_stage) (void)hipHostFree(g_stage);
+            g_stage = nullptr;
+            g_stage_bytes = 0;
+            e = hipHostMalloc(&g_stage, jb + sb, hipHostMallocDefault);
+            if (e == hipSuccess) g_stage_bytes = jb + sb;
+        }
+        if (e == hipSuccess && !g_stage_done) e = hipEventCreateWithFlags(&g_stage_done, hipEventDisableTiming);
+        if (e == hipSuccess) {
+            std::memcpy(g_stage, dj.data(), jb);
+            std::memcpy(static_cast<char*>(g_stage) + jb, segs.data(), sb);
+            e = hipMemcpyAsync(ws + L.jobs_off, g_stage, jb, hipMemcpyHostToDevice, s);
+        }
+        if (e == hipSuccess && sb)
+            e = hipMemcpyAsync(ws + L.segs_off, static_cast<char*>(g_stage) + jb, sb,
+                               hipMemcpyHostToDevice, s);
+        if (e == hipSuccess) e = hipEventRecord(g_stage_done, s);
+        if ((rc = device_status(e, "batch tables"))) return rc;
+    }
+    return device_status(bpm::launch_batch((const bpm::BatchJob*)(ws + L.jobs_off),
+                                           (const bpm::BatchSeg*)(ws + L.segs_off), first,
+                                           (unsigned*)(ws + L.q_off), n_jobs, s),
+                         "batch march");
 }
 
 static int checkpoint_interval(int steps, int checkpoint_every) {

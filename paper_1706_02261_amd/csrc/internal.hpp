@@ -61,6 +61,29 @@ hipError_t launch_adjoint(const Geom& g, const Plan& p, const AdjointIO& io, int
 hipError_t launch_fft2(const void* in, void* out, int nx, int ny, bool inverse, float scale,
                        const Plan& p, hipStream_t s);
 
+// Uneven batch (batch.hip).  Device copy of one job and one segment of the
+// item list: the `count` items of pass `pass` of job `job` start at item
+// `first`; they may run once the job has completed `need` items.
+struct BatchJob {
+    const void* field_in;
+    const float* dn;
+    void* work;  // the job's field_out
+    float* inten;
+    const void* H;
+    const void* twx;
+    const void* twy;
+    int nx, ny, steps;
+    float k0dz;
+};
+struct BatchSeg {
+    int job, pass, first, count, need;
+};
+int batch_queue_words(int n_jobs);
+int row_units(int nx, int ny);
+int col_units(int nx, int ny);
+hipError_t launch_batch(const BatchJob* jobs_dev, const BatchSeg* segs_dev, int total,
+                        unsigned* q, int n_jobs, hipStream_t s);
+
 // Pupil plane of the adaptive-optics gradient.
 hipError_t launch_pupil_spectrum(const float* amp, const float* phase, const Geom& g, double z_f,
                                  void* U, hipStream_t s);

@@ -1,0 +1,275 @@
+// Device building blocks shared by the persistent kernels: the fused row and
+// column passes of one march step (forward and adjoint), agent-coherent field
+// access and the grid barrier.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <type_traits>
+
+#include "fft.hpp"
+#include "mathx.hpp"
+
+namespace bpm {
+
+constexpr int kR = 16;           // complex values per thread
+constexpr int kBlock = 256;      // threads per workgroup
+constexpr int kBarWords = 1024;  // grid-barrier words (4 KiB) in the plan
+
+template <int N>
+constexpr int units_per_block() { return kBlock / (N / kR); }
+
+// The field travels between the passes of a persistent march through global
+// memory while the kernel runs.  The L2 caches of the eight XCDs are not
+// coherent with each other, so every access to a buffer written inside the
+// kernel is an agent-scope relaxed atomic (a load that does not hit a stale
+// L2 line, a store that writes through to the device coherence point).
+// Read-only data (propagator, twiddles, dn, dL/dI) keeps ordinary cached
+// loads.
+__device__ __forceinline__ float2 ld_shared_field(const float2* p) {
+    const unsigned long long v = __hip_atomic_load(reinterpret_cast<const unsigned long long*>(p),
+                                                   __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    return __builtin_bit_cast(float2, v);
+}
+__device__ __forceinline__ void st_shared_field(float2* p, float2 v) {
+    __hip_atomic_store(reinterpret_cast<unsigned long long*>(p),
+                       __builtin_bit_cast(unsigned long long, v), __ATOMIC_RELAXED,
+                       __HIP_MEMORY_SCOPE_AGENT);
+}
+
+// ---------------------------------------------------------------------------
+// pass bodies
+//
+// Every workgroup has 256 threads.  A row unit is B = 256 / (nx/16) rows, a
+// column unit W = 256 / (ny/16) columns; units past the field's edge compute
+// on row / column 0, store nothing and still take part in the barriers.
+
+// workgroup-wide and wavefront-wide LDS ordering points
+struct BlockSync {
+    __device__ __forceinline__ void operator()() const { __syncthreads(); }
+};
+struct WaveSync {
+    __device__ __forceinline__ void operator()() const {
+        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+        __builtin_amdgcn_wave_barrier();
+        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+    }
+};
+
+// row FFTs of at most one wavefront only need wavefront-wide LDS ordering
+template <int N>
+using RowSync = typename std::conditional<(N / kR <= 64), WaveSync, BlockSync>::type;
+
+// screen: v[i] *= exp(i ph[i]); when every phase of the wavefront lies in
+// [-pi/4, pi/4] (the usual case: k0 dz dn is a fraction of a radian) the
+// range reduction is skipped.
+__device__ __forceinline__ void apply_screen(float2 (&v)[kR], const float (&ph)[kR]) {
+    bool small = true;
+#pragma unroll
+    for (int i = 0; i < kR; ++i) small &= fabsf(ph[i]) <= kQuarterPi;
+    if (__all(small)) {
+#pragma unroll
+        for (int i = 0; i < kR; ++i) v[i] = c_mul(v[i], cos_sin_quarter(ph[i]));
+    } else {
+#pragma unroll
+        for (int i = 0; i < kR; ++i) v[i] = c_mul(v[i], expi(ph[i]));
+    }
+}
+
+// dn of this thread's row unit, fetched ahead of the row pass
+template <int NX>
+__device__ __forceinline__ void load_dn(float (&d)[kR], int unit, int ny,
+                                        const float* __restrict__ dn) {
+    constexpr int T = NX / kR, B = units_per_block<NX>();
+    const int row = unit * B + threadIdx.x / T, tau = threadIdx.x % T;
+    const size_t rowoff = (size_t)(row < ny ? row : 0) * NX;
+#pragma unroll
+    for (int i = 0; i < kR; ++i) d[i] = dn[rowoff + i * T + tau];
+}
+
+// What a row pass takes, does and leaves.
+enum RowIn : int { kSpecIn = 0, kNaturalIn = 1, kZeroIn = 2 };
+enum RowOps : int { kNoOps = 0, kScreen = 1, kAdjointOps = 2 };
+enum RowOut : int { kSpecOut = 0, kNaturalOut = 1, kNoOut = 2 };
+
+struct RowArgs {
+    const float2* src;  // spectrum (working buffer) or natural field
+    float2* dst;        // spectrum (working buffer) or natural field
+    float* inten;       // forward: I slice, or null
+    float2* keep;       // forward: copy of the natural u_{j+1}, or null
+    const float2* u;    // adjoint: natural u_{j+1}
+    const float* gI;    // adjoint: dL/dI slice, or null
+    float* gdn;         // adjoint: dL/ddn slice, or null
+    float k0dz;
+};
+
+template <int NX, int IN, int OPS, int OUT>
+__device__ __forceinline__ void row_unit(int unit, int ny, const RowArgs& a,
+                                         const float (&d)[kR], const Twiddles<NX, kR>& twx,
+                                         float2* smem) {
+    constexpr int T = NX / kR, B = units_per_block<NX>();
+    const int sub = threadIdx.x / T, tau = threadIdx.x % T;
+    const int row = unit * B + sub;
+    const bool on = row < ny;
+    const size_t rowoff = (size_t)(on ? row : 0) * NX;
+    float2* lds = smem + sub * lds_size<NX>();
+    const RowSync<NX> sync;
+    float2 v[kR];
+    if constexpr (IN == kZeroIn) {
+#pragma unroll
+        for (int i = 0; i < kR; ++i) v[i] = make_float2(0.f, 0.f);
+    } else if constexpr (IN == kNaturalIn) {
+#pragma unroll
+        for (int i = 0; i < kR; ++i) v[i] = ld_shared_field(a.src + rowoff + i * T + tau);
+    } else {
+#pragma unroll
+        for (int r = 0; r < kR; ++r) v[r] = ld_shared_field(a.src + rowoff + r * T + tau);
+        fft_inverse<NX, kR, 1>(v, lds, tau, twx, sync);
+    }
+    if constexpr (OPS == kScreen) {
+        float ph[kR];
+#pragma unroll
+        for (int i = 0; i < kR; ++i) ph[i] = a.k0dz * d[i];
+        apply_screen(v, ph);
+        if (a.inten && on) {
+#pragma unroll
+            for (int i = 0; i < kR; ++i) a.inten[rowoff + i * T + tau] = c_abs2(v[i]);
+        }
+        if (a.keep && on) {
+#pragma unroll
+            for (int i = 0; i < kR; ++i) st_shared_field(a.keep + rowoff + i * T + tau, v[i]);
+        }
+    } else if constexpr (OPS == kAdjointOps) {
+        float2 u[kR];
+#pragma unroll
+        for (int i = 0; i < kR; ++i) u[i] = ld_shared_field(a.u + rowoff + i * T + tau);
+        if (a.gI) {
+#pragma unroll
+            for (int i = 0; i < kR; ++i) {
+                const float w = 2.f * a.gI[rowoff + i * T + tau];
+                v[i] = make_float2(fmaf(w, u[i].x, v[i].x), fmaf(w, u[i].y, v[i].y));
+            }
+        }
+        if (a.gdn && on) {
+#pragma unroll
+            for (int i = 0; i < kR; ++i)
+                a.gdn[rowoff + i * T + tau] = a.k0dz * fmaf(v[i].y, u[i].x, -v[i].x * u[i].y);
+        }
+        float ph[kR];
+#pragma unroll
+        for (int i = 0; i < kR; ++i) ph[i] = -a.k0dz * d[i];
+        apply_screen(v, ph);
+    }
+    if constexpr (OUT == kSpecOut) {
+        fft_forward<NX, kR, 1>(v, lds, tau, twx, sync);
+        if (on) {
+#pragma unroll
+            for (int r = 0; r < kR; ++r) st_shared_field(a.dst + rowoff + r * T + tau, v[r]);
+        }
+    } else if constexpr (OUT == kNaturalOut) {
+        if (on) {
+#pragma unroll
+            for (int i = 0; i < kR; ++i) a.dst[rowoff + i * T + tau] = v[i];
+        }
+    }
+}
+
+// Column pass on a working buffer: forward column FFTs, x H (or conj(H)),
+// inverse column FFTs.  With spec_out, the multiplied spectrum is also written
+// to spec_out in natural DFT order (the pupil-plane gradient).
+template <int NY, bool CONJ>
+__device__ __forceinline__ void col_unit(int unit, int nx, float2* work,
+                                         const float2* __restrict__ H,
+                                         const Twiddles<NY, kR>& twy, float2* smem,
+                                         float2* spec_out, const int* __restrict__ permx,
+                                         const int* __restrict__ permy) {
+    constexpr int T = NY / kR, W = units_per_block<NY>();
+    const int w = threadIdx.x % W, t = threadIdx.x / W;
+    const int c = unit * W + w;
+    const bool on = c < nx;
+    const size_t col = on ? (size_t)c : 0;
+    float2* lds = smem + w;
+    const BlockSync sync;
+    float2 v[kR], h[kR];
+#pragma unroll
+    for (int i = 0; i < kR; ++i) v[i] = ld_shared_field(work + (size_t)(i * T + t) * nx + col);
+#pragma unroll
+    for (int r = 0; r < kR; ++r) h[r] = H[(size_t)(r * T + t) * nx + col];
+    fft_forward<NY, kR, W>(v, lds, t, twy, sync);
+#pragma unroll
+    for (int r = 0; r < kR; ++r) v[r] = CONJ ? c_mulc(v[r], h[r]) : c_mul(v[r], h[r]);
+    if (spec_out && on) {
+        const size_t m = (size_t)permx[col];
+#pragma unroll
+        for (int r = 0; r < kR; ++r) spec_out[(size_t)permy[r * T + t] * nx + m] = v[r];
+    }
+    fft_inverse<NY, kR, W>(v, lds, t, twy, sync);
+    if (on) {
+#pragma unroll
+        for (int i = 0; i < kR; ++i) st_shared_field(work + (size_t)(i * T + t) * nx + col, v[i]);
+    }
+}
+
+// ---------------------------------------------------------------------------
+// grid barrier of the persistent marches
+//
+// Two levels, no cache maintenance.  Workgroup b belongs to group b % 8 (the
+// XCD the hardware deals it to).  Each arrival bumps its group's counter; the
+// last arrival of a group bumps the global counter; the last group's closer
+// publishes the barrier's generation to eight per-group flags, which the
+// groups poll.  Every counter and flag sits in its own 128-byte line.  All of
+// a wave's stores are complete (s_waitcnt) before its workgroup arrives, and
+// buffers written inside the kernel are only accessed with agent-coherent
+// operations, so no L2 write-back or invalidation is needed.
+//
+// Every workgroup is resident (cooperative launch), so the wait ends; as a
+// guard against a launch that is not, the spin is bounded and a time-out is
+// recorded in the error word and ends all further waiting, so the kernel
+// always exits.
+//
+// Barrier words (unsigned, zeroed by the plan kernel before every march):
+//   [32 * g]        arrivals of group g        (g < 8)
+//   [256 + 32 * g]  released generation of g
+//   [512]           closed groups
+//   [544]           time-out flag
+
+constexpr unsigned kSpinLimit = 1u << 22;
+
+__device__ __forceinline__ void grid_sync(unsigned* bar, unsigned gen, bool& abort) {
+    __builtin_amdgcn_s_waitcnt(0);
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        const unsigned G = gridDim.x, g = blockIdx.x & 7u;
+        const unsigned groups = G < 8u ? G : 8u;
+        const unsigned members = (G - g + 7u) / 8u;
+        const unsigned old = __hip_atomic_fetch_add(bar + 32 * g, 1u, __ATOMIC_RELAXED,
+                                                    __HIP_MEMORY_SCOPE_AGENT);
+        if (old + 1u == gen * members) {
+            const unsigned o2 = __hip_atomic_fetch_add(bar + 512, 1u, __ATOMIC_RELAXED,
+                                                       __HIP_MEMORY_SCOPE_AGENT);
+            if (o2 + 1u == gen * groups)
+                for (unsigned k = 0; k < groups; ++k)
+                    __hip_atomic_store(bar + 256 + 32 * k, gen, __ATOMIC_RELAXED,
+                                       __HIP_MEMORY_SCOPE_AGENT);
+        }
+        unsigned spins = 0;
+        while (!abort && __hip_atomic_load(bar + 256 + 32 * g, __ATOMIC_RELAXED,
+                                           __HIP_MEMORY_SCOPE_AGENT) < gen) {
+            if (++spins > kSpinLimit) {
+                __hip_atomic_store(bar + 544, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+                abort = true;
+            }
+        }
+    }
+    __syncthreads();
+}
+
+// XCD-aware unit order: workgroups are dealt round-robin over the 8 XCDs, so
+// give each XCD a contiguous range of units (neighbouring columns share cache
+// lines).
+__device__ __forceinline__ int virtual_block() {
+    const int G = gridDim.x, b = blockIdx.x;
+    return (G % 8 == 0) ? (b % 8) * (G / 8) + b / 8 : b;
+}
+
+}  // namespace bpm

@@ -1,0 +1,145 @@
+"""C-ABI contract checks that need no GPU.
+
+The library loads on a host without a GPU, exports every function that
+include/bpm.h declares, and rejects bad arguments on the host before any HIP
+call is made.  Pointers here are host addresses used only as non-null,
+aligned placeholders: every call below fails validation first.
+"""
+import ctypes
+import math
+import os
+import re
+
+import numpy as np
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "include", "bpm.h")
+
+
+@pytest.fixture(scope="module")
+def L():
+    from paper_1706_02261_amd import _lib
+    return _lib.lib()
+
+
+def declared_functions():
+    text = open(HEADER).read()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    return sorted(set(re.findall(r"^\s*(?:const\s+)?\w+\*?\s+\**(\w+)\s*\(", text, flags=re.M)))
+
+
+def test_every_declared_symbol_is_exported(L):
+    names = declared_functions()
+    assert "bpm_propagate" in names and "bpm_adjoint" in names and len(names) >= 13
+    for n in names:
+        assert hasattr(L, n), n
+
+
+def test_binding_lists_every_export():
+    from paper_1706_02261_amd import _lib
+    assert set(declared_functions()) == set(_lib.EXPORTS)
+
+
+def test_error_strings(L):
+    for code in (0, -1, -2, -3, -4, -5):
+        assert L.bpm_error_string(code)
+    assert L.bpm_error_string(-99) == b"unknown error code"
+
+
+@pytest.mark.parametrize("nx,ny", [(16, 64), (64, 4096), (100, 128), (0, 64), (-64, 64)])
+def test_workspace_size_rejects_unsupported_sizes(L, nx, ny):
+    assert L.bpm_workspace_size(nx, ny, 8, 0) == 0
+
+
+def test_workspace_sizes(L):
+    fwd = L.bpm_workspace_size(1024, 1024, 1024, 0)
+    assert fwd >= 8 * 1024 * 1024                      # the propagator table
+    adj = L.bpm_adjoint_workspace_size(256, 256, 512, 0)
+    k = math.ceil(math.sqrt(512))
+    fields = math.ceil(512 / k) + k + 2
+    assert adj >= fields * 256 * 256 * 8
+    assert L.bpm_workspace_size(256, 256, 512, 1) == adj
+    assert L.bpm_adjoint_workspace_size(256, 256, 512, 513) == 0
+    assert L.bpm_adjoint_workspace_size(256, 256, 512, 1) > adj
+
+
+class Buf:
+    """Host placeholder memory, aligned, never dereferenced by these calls."""
+
+    def __init__(self, n=4096):
+        self.a = np.zeros(n + 64, np.uint8)
+        base = self.a.ctypes.data
+        self.p = base + (-base) % 256
+
+    def __int__(self):
+        return self.p
+
+
+def call_propagate(L, nx=64, ny=64, steps=2, dx=0.2, dz=0.2, lam=0.5, n0=1.33,
+                   fin=True, dn=True, fout=True, ws_bytes=None):
+    b = Buf()
+    ws = b.p if ws_bytes != -1 else None
+    wsb = L.bpm_workspace_size(64, 64, 2, 0) if ws_bytes is None else max(ws_bytes, 0)
+    return L.bpm_propagate(b.p if fin else None, b.p if dn else None, nx, ny, steps, dx, dz, lam,
+                           n0, b.p if fout else None, None, ws, wsb, None)
+
+
+def test_propagate_validation(L):
+    from paper_1706_02261_amd import _lib as B
+    assert call_propagate(L, nx=100) == B.BPM_ERR_UNSUPPORTED_SIZE
+    assert call_propagate(L, ny=4096) == B.BPM_ERR_UNSUPPORTED_SIZE
+    assert call_propagate(L, steps=-1) == B.BPM_ERR_INVALID_ARG
+    assert call_propagate(L, dx=float("nan")) == B.BPM_ERR_NOT_FINITE
+    assert call_propagate(L, dz=float("inf")) == B.BPM_ERR_NOT_FINITE
+    assert call_propagate(L, lam=0.0) == B.BPM_ERR_NOT_FINITE
+    assert call_propagate(L, n0=-1.0) == B.BPM_ERR_NOT_FINITE
+    assert call_propagate(L, fin=False) == B.BPM_ERR_INVALID_ARG
+    assert call_propagate(L, fout=False) == B.BPM_ERR_INVALID_ARG
+    assert call_propagate(L, dn=False) == B.BPM_ERR_INVALID_ARG
+    assert call_propagate(L, ws_bytes=16) == B.BPM_ERR_WORKSPACE
+    assert call_propagate(L, ws_bytes=-1) == B.BPM_ERR_WORKSPACE
+    assert b"workspace" in L.bpm_last_error()
+
+
+def test_adjoint_validation(L):
+    from paper_1706_02261_amd import _lib as B
+    b = Buf()
+    ws = L.bpm_adjoint_workspace_size(64, 64, 4, 0)
+    rc = L.bpm_adjoint(b.p, b.p, 64, 64, 4, 0.2, 0.2, 0.5, 1.33, None, None, b.p, None, None,
+                       5, b.p, ws, None)
+    assert rc == B.BPM_ERR_INVALID_ARG and b"checkpoint_every" in L.bpm_last_error()
+    rc = L.bpm_adjoint(None, b.p, 64, 64, 4, 0.2, 0.2, 0.5, 1.33, None, None, b.p, None, None,
+                       0, b.p, ws, None)
+    assert rc == B.BPM_ERR_INVALID_ARG
+    rc = L.bpm_adjoint(b.p, b.p, 64, 64, 4, 0.2, 0.2, 0.5, 1.33, None, None, b.p, None, None,
+                       0, b.p, 100, None)
+    assert rc == B.BPM_ERR_WORKSPACE
+
+
+def test_batch_validation(L):
+    from paper_1706_02261_amd import _lib as B
+    b = Buf()
+    jobs = (B.Job * 2)()
+    jobs[0] = B.Job(b.p, b.p, 64, 64, 3, 0.2, 0.2, 0.5, 1.33, b.p, 0)
+    jobs[1] = B.Job(b.p, b.p, 48, 64, 3, 0.2, 0.2, 0.5, 1.33, b.p, 0)
+    assert L.bpm_batch_workspace_size(jobs, 2) == 0
+    assert L.bpm_propagate_batch(jobs, 2, b.p, 1 << 30, None) == B.BPM_ERR_UNSUPPORTED_SIZE
+    assert b"job 1" in L.bpm_last_error()
+    assert L.bpm_propagate_batch(jobs, 0, b.p, 1 << 30, None) == B.BPM_ERR_INVALID_ARG
+    jobs[1] = B.Job(b.p, None, 64, 64, 3, 0.2, 0.2, 0.5, 1.33, b.p, 0)
+    assert L.bpm_propagate_batch(jobs, 2, b.p, 1 << 30, None) == B.BPM_ERR_INVALID_ARG
+    jobs[1] = B.Job(b.p, b.p, 64, 64, 3, 0.2, 0.2, 0.5, 1.33, b.p, 0)
+    need = L.bpm_batch_workspace_size(jobs, 2)
+    assert need > 2 * L.bpm_workspace_size(64, 64, 3, 0)
+    assert L.bpm_propagate_batch(jobs, 2, b.p, need - 1, None) == B.BPM_ERR_WORKSPACE
+
+
+def test_helper_validation(L):
+    from paper_1706_02261_amd import _lib as B
+    b = Buf()
+    assert L.bpm_fft2(b.p, b.p, 64, 48, 0, b.p, 1 << 20, None) == B.BPM_ERR_UNSUPPORTED_SIZE
+    assert L.bpm_fft2(b.p, b.p, 64, 64, 2, b.p, 1 << 20, None) == B.BPM_ERR_INVALID_ARG
+    assert L.bpm_pupil_spectrum(b.p, b.p, 64, 64, 0.2, 0.5, 1.33, float("nan"), b.p, None) == \
+        B.BPM_ERR_NOT_FINITE
+    assert L.bpm_pupil_phase_grad(None, b.p, 64, 64, b.p, None) == B.BPM_ERR_INVALID_ARG

@@ -1,0 +1,88 @@
+"""GPU parity of the uneven batch (bpm_propagate_batch).
+
+Every job of a batch must equal, bit for bit, its own bpm_propagate call
+(same kernels, same plan), and therefore the oracle within the march's
+tolerance; jobs of every size class, a zero-step job and repeated launches
+on the same workspace are covered.
+"""
+import numpy as np
+import pytest
+
+import oracle
+import synth
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+
+
+def rel(a, b):
+    return float(np.linalg.norm(a - b) / np.linalg.norm(b))
+
+
+def make_jobs(shapes, seed):
+    rng = np.random.default_rng(seed)
+    jobs = []
+    for (nx, ny, steps) in shapes:
+        u0 = (rng.standard_normal((ny, nx)) + 1j * rng.standard_normal((ny, nx))).astype(np.complex64)
+        dn = rng.uniform(0, 0.05, (steps, ny, nx)).astype(np.float32)
+        dx = float(rng.choice([0.1, 0.2]))
+        jobs.append(dict(u0=u0, dn_h=dn, field=torch.from_numpy(u0).cuda(),
+                         dn=torch.from_numpy(dn).cuda(), dx=dx, dz=0.2, wavelength=0.5, n0=1.33))
+    return jobs
+
+
+def separate(job):
+    import paper_1706_02261_amd as bpm
+    out, inten = bpm.propagate(job["field"], job["dn"], job["dx"], job["dz"], job["wavelength"],
+                               job["n0"])
+    return out.cpu().numpy(), inten.cpu().numpy()
+
+
+SHAPES = [(64, 128, 5), (256, 256, 12), (32, 32, 0), (128, 64, 7), (512, 128, 3),
+          (1024, 32, 2), (32, 2048, 4), (256, 512, 9)]
+
+
+def test_batch_equals_separate_calls_and_oracle():
+    import paper_1706_02261_amd as bpm
+    jobs = make_jobs(SHAPES, seed=1)
+    res = bpm.propagate_batch(jobs)
+    torch.cuda.synchronize()
+    for job, (out, inten) in zip(jobs, res):
+        o, i = out.cpu().numpy(), inten.cpu().numpy()
+        so, si = separate(job)
+        assert np.array_equal(o, so) and np.array_equal(i, si), job["u0"].shape
+        steps = job["dn_h"].shape[0]
+        if steps == 0:
+            assert np.array_equal(o, job["u0"])
+            continue
+        ro, ri = oracle.bpm_forward(job["u0"], job["dn_h"], job["dx"], job["dz"], 0.5, 1.33)
+        assert rel(o, ro) <= 2e-6 and rel(i, ri) <= 4e-6
+
+
+def test_batch_repeated_launches_on_one_workspace():
+    """Queue and completion counters are reset by every launch."""
+    import paper_1706_02261_amd as bpm
+    from paper_1706_02261_amd import _lib
+    from paper_1706_02261_amd.bpm import workspace
+    jobs = make_jobs([(256, 256, 20), (512, 512, 6), (128, 256, 33)], seed=2)
+    first = [(o.clone(), i.clone()) for o, i in bpm.propagate_batch(jobs)]
+    torch.cuda.synchronize()
+    for _ in range(3):
+        again = bpm.propagate_batch(jobs)
+        torch.cuda.synchronize()
+        for (a, ai), (b, bi) in zip(first, again):
+            assert torch.equal(a, b) and torch.equal(ai, bi)
+
+
+def test_batch_of_the_uneven_mix():
+    """16 jobs drawn like the paper-scale batch (sizes 256-1024, random depth),
+    each compared bitwise with its own march."""
+    import paper_1706_02261_amd as bpm
+    specs = synth.batch_job_specs(n_jobs=16, steps_range=(4, 24), budget_bytes=4e9, seed_child=11)
+    jobs = make_jobs(specs, seed=3)
+    res = bpm.propagate_batch(jobs)
+    torch.cuda.synchronize()
+    for job, (out, inten) in zip(jobs, res):
+        so, si = separate(job)
+        assert np.array_equal(out.cpu().numpy(), so) and np.array_equal(inten.cpu().numpy(), si)
