@@ -173,6 +173,28 @@ int bpm_pupil_spectrum(const float* amplitude, const float* phase, int nx, int n
 int bpm_pupil_phase_grad(const bpm_c64* grad_spectrum, const bpm_c64* spectrum, int nx, int ny,
                          float* grad_phase, void* hip_stream);
 
+/* Bytes of workspace for bpm_psf_readout. */
+size_t bpm_psf_readout_workspace_size(int nx, int ny, int planes);
+
+/* PSF readout of a multiplexed run through the idealised refocusing lens of
+ * the detection path (main-text paragraph on the light-sheet simulation: the
+ * multiplexed point sources are propagated through the sample and an
+ * idealised, refocusing lens to the camera, giving the spatially varying
+ * PSFs).  exit_field is the field after a march that started at the source
+ * plane back_steps slices earlier.  With P the detection pupil
+ * [kx^2 + ky^2 <= (2 pi NA / wavelength)^2] (integer test as for the
+ * propagator):
+ *   S   = DFT2(exit) . P . exp(-i kz back_steps dz)
+ *   E_m = IDFT2(S . exp(i kz m dz)),  m = -planes/2 .. planes/2 - 1
+ *   psf[s][m + planes/2][y][x] = scale |E_m(sy - crop/2 + y, sx - crop/2 + x)|^2
+ * (periodic indices).  sources: device int32 [n_src][2] = (sy, sx) pixels;
+ * psf_out: device float32 [n_src][planes][crop][crop]; planes in 1..256,
+ * crop in 1..min(nx, ny).  Workspace: bpm_psf_readout_workspace_size bytes. */
+int bpm_psf_readout(const bpm_c64* exit_field, int nx, int ny, double dx, double dz,
+                    double wavelength, double n0, double na, int back_steps, const int* sources,
+                    int n_src, int planes, int crop, double scale, float* psf_out,
+                    void* workspace, size_t workspace_bytes, void* hip_stream);
+
 /* Learned PSF surrogate, inference (the paper's sets of 10^5 - 10^6 spatially
  * varying PSFs, abstract and main-text paragraph on image formation).
  *   weights_bf16   device blob written by the surrogate trainer (format in

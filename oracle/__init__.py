@@ -69,6 +69,9 @@ def _declare(L):
     L.oracle_bpm_adjoint.argtypes = [_dp, _dp, _I, _I, _I, _D, _D, _D, _D,
                                      _dp, _dp, _dp, _dp, _dp]
     L.oracle_set_threads.argtypes = [_I]
+    L.oracle_psf_readout.argtypes = [_dp, _I, _I, _D, _D, _D, _D, _D, _I,
+                                     ctypes.POINTER(ctypes.c_int), _I, _I, _I, _D, _dp]
+    L.oracle_psf_readout.restype = _I
     for name in ("oracle_set_threads", "oracle_fft1d", "oracle_fft2d", "oracle_propagator",
                  "oracle_bpm_forward", "oracle_bpm_adjoint"):
         getattr(L, name).restype = _I
@@ -77,11 +80,10 @@ def _declare(L):
 
 
 def _declare_conv(L):
-    # int oracle_conv3d_forward(x, w, b, out, N, Ci, D, H, W, Co, kd, kh, kw,
-    #                           sd, sh, sw, pd, ph, pw, relu)
-    geo = [_I] * 16
-    L.oracle_conv3d_forward.argtypes = [_dp, _dp, _dp, _dp] + geo
-    L.oracle_conv3d_backward.argtypes = [_dp, _dp, _dp, _dp, _dp, _dp, _dp] + geo
+    # forward(x, w, b, y, N, Ci, D, H, W, Co, kd, kh, kw, sd, sh, sw, pd, ph, pw, relu)
+    # backward(x, w, dy, dx, dw, db, N, Ci, D, H, W, Co, kd, kh, kw, sd, sh, sw, pd, ph, pw)
+    L.oracle_conv3d_forward.argtypes = [_dp, _dp, _dp, _dp] + [_I] * 16
+    L.oracle_conv3d_backward.argtypes = [_dp] * 6 + [_I] * 15
     L.oracle_conv3d_forward.restype = _I
     L.oracle_conv3d_backward.restype = _I
 
@@ -161,6 +163,55 @@ def bpm_adjoint(u0, dn, dx, dz, wavelength, n0, grad_u_out=None, grad_intensity=
                                   _ptr(s0.view(np.float64)), _ptr(gdn))
     _check(rc, "bpm_adjoint")
     return g0, s0, gdn
+
+
+def psf_readout(exit_field, dx, dz, wavelength, n0, na, back_steps, sources, planes=32,
+                crop=32, scale=1.0):
+    """Refocused PSF stacks of a multiplexed run: [n_src][planes][crop][crop]."""
+    u = _c128(exit_field)
+    ny, nx = u.shape
+    src = np.ascontiguousarray(np.asarray(sources, dtype=np.int32).reshape(-1, 2))
+    out = np.empty((len(src), planes, crop, crop), dtype=np.float64)
+    rc = lib().oracle_psf_readout(_ptr(u.view(np.float64)), nx, ny, dx, dz, wavelength, n0, na,
+                                  int(back_steps), src.ctypes.data_as(ctypes.POINTER(ctypes.c_int)),
+                                  len(src), planes, crop, float(scale), _ptr(out))
+    _check(rc, "psf_readout")
+    return out
+
+
+def _conv_geo(x_shape, w_shape, stride, pad):
+    N, Ci, D, H, W = x_shape
+    Co, Ci2, kd, kh, kw = w_shape
+    if Ci2 != Ci:
+        raise ValueError("channel mismatch")
+    sd, sh, sw = stride
+    pd, ph, pw = pad
+    out = (N, Co, (D + 2 * pd - kd) // sd + 1, (H + 2 * ph - kh) // sh + 1,
+           (W + 2 * pw - kw) // sw + 1)
+    return [N, Ci, D, H, W, Co, kd, kh, kw, sd, sh, sw, pd, ph, pw], out
+
+
+def conv3d_forward(x, w, b=None, stride=(1, 1, 1), pad=(1, 1, 1), relu=False):
+    """Direct-loop 3-D cross-correlation (NCDHW), float64."""
+    x, w = _f64(x), _f64(w)
+    b = None if b is None else _f64(b)
+    geo, out_shape = _conv_geo(x.shape, w.shape, stride, pad)
+    y = np.empty(out_shape)
+    _check(lib().oracle_conv3d_forward(_ptr(x), _ptr(w), _ptr(b), _ptr(y), *geo, int(relu)),
+           "conv3d_forward")
+    return y
+
+
+def conv3d_backward(x, w, dy, stride=(1, 1, 1), pad=(1, 1, 1)):
+    """Gradients (dx, dw, db) of the convolution for an upstream gradient dy."""
+    x, w, dy = _f64(x), _f64(w), _f64(dy)
+    geo, out_shape = _conv_geo(x.shape, w.shape, stride, pad)
+    if dy.shape != out_shape:
+        raise ValueError(f"dy has shape {dy.shape}, expected {out_shape}")
+    dx, dw, db = np.empty(x.shape), np.empty(w.shape), np.empty(w.shape[0])
+    _check(lib().oracle_conv3d_backward(_ptr(x), _ptr(w), _ptr(dy), _ptr(dx), _ptr(dw), _ptr(db),
+                                        *geo), "conv3d_backward")
+    return dx, dw, db
 
 
 def set_threads(n: int = 0) -> int:

@@ -290,3 +290,81 @@ int oracle_set_threads(int n) {
     return 1;
 #endif
 }
+
+/* ------------------------------------------------------------------------ */
+/* PSF readout of a multiplexed run                                          */
+/*
+ * The detection path images the source plane through an idealised lens
+ * (main-text paragraph on the light-sheet simulation: light of the
+ * multiplexed point sources propagated through the sample and a refocusing
+ * lens to the camera).  From the exit field u of a march that started at the
+ * source plane `back_steps` slices earlier:
+ *
+ *   S    = DFT2(u) . P . exp(-i kz back_steps dz),  P = [kx^2 + ky^2 <= (k0 NA)^2]
+ *   (P evaluated on integers like the propagating test:
+ *    (m~ ny)^2 + (l~ nx)^2 <= (nx ny NA dx / lambda)^2)
+ *   E_m  = IDFT2( S . exp(i kz m dz) ),   m = -planes/2 .. planes/2 - 1
+ *   psf[i][m + planes/2][y][x] = scale |E_m(sy_i - crop/2 + y, sx_i - crop/2 + x)|^2
+ *
+ * (periodic indices; kz = sqrt(k^2 - kx^2 - ky^2), k = n0 k0).  src holds
+ * (sy, sx) pixel pairs.  psf_out: [n_src][planes][crop][crop].
+ */
+int oracle_psf_readout(const double *exit_field, int nx, int ny, double dx, double dz,
+                       double lam, double n0, double na, int back_steps, const int *src,
+                       int n_src, int planes, int crop, double scale, double *psf_out) {
+    if (!exit_field || !src || !psf_out || !is_pow2(nx) || !is_pow2(ny) || planes < 1 ||
+        crop < 1 || n_src < 0 || !(dx > 0) || !(lam > 0) || !(n0 > 0) || !(na > 0))
+        return ORACLE_ERR_ARG;
+    long n = (long)nx * ny;
+    cplx *S = (cplx *)malloc(sizeof(cplx) * (size_t)n);
+    cplx *E = (cplx *)malloc(sizeof(cplx) * (size_t)n);
+    if (!S || !E) { free(S); free(E); return ORACLE_ERR_MEM; }
+    memcpy(S, exit_field, sizeof(cplx) * (size_t)n);
+    int rc = fft2d(S, nx, ny, -1);
+    double k0 = 2.0 * PI / lam, k = n0 * k0;
+    double pthr = (double)nx * (double)ny * na * dx / lam;
+    pthr *= pthr;
+    for (int l = 0; l < ny && rc == 0; l++) {
+        double ky = 2.0 * PI * (double)signed_index(l, ny) / (ny * dx);
+        for (int m = 0; m < nx; m++) {
+            double kx = 2.0 * PI * (double)signed_index(m, nx) / (nx * dx);
+            double kt2 = kx * kx + ky * ky;
+            long i = (long)l * nx + m;
+            if (prop_mask(m, l, nx, ny, pthr)) {
+                double kz = sqrt(fmax(k * k - kt2, 0.0));
+                double ph = -kz * back_steps * dz;
+                S[i] *= cos(ph) + I * sin(ph);
+            } else {
+                S[i] = 0.0;
+            }
+        }
+    }
+    for (int p = 0; p < planes && rc == 0; p++) {
+        int mz = p - planes / 2;
+        for (int l = 0; l < ny; l++) {
+            double ky = 2.0 * PI * (double)signed_index(l, ny) / (ny * dx);
+            for (int m = 0; m < nx; m++) {
+                double kx = 2.0 * PI * (double)signed_index(m, nx) / (nx * dx);
+                double kz = sqrt(fmax(k * k - kx * kx - ky * ky, 0.0));
+                double ph = kz * mz * dz;
+                long i = (long)l * nx + m;
+                E[i] = S[i] * (cos(ph) + I * sin(ph));
+            }
+        }
+        rc = fft2d(E, nx, ny, +1);
+        for (int s = 0; s < n_src && rc == 0; s++) {
+            int sy = src[2 * s], sx = src[2 * s + 1];
+            for (int y = 0; y < crop; y++) {
+                int gy = ((sy - crop / 2 + y) % ny + ny) % ny;
+                for (int x = 0; x < crop; x++) {
+                    int gx = ((sx - crop / 2 + x) % nx + nx) % nx;
+                    cplx e = E[(long)gy * nx + gx] / (double)n;
+                    double v = creal(e) * creal(e) + cimag(e) * cimag(e);
+                    psf_out[(((long)s * planes + p) * crop + y) * crop + x] = scale * v;
+                }
+            }
+        }
+    }
+    free(S); free(E);
+    return rc;
+}

@@ -6,8 +6,8 @@ torch tensors (device memory and streams) into the C ABI.
 """
 from ._lib import BpmError, lib  # noqa: F401
 from .bpm import (BPMFunction, PupilBPMFunction, adjoint, fft2, propagate,  # noqa: F401
-                  propagate_batch,
+                  propagate_batch, psf_readout,
                   pupil_phase_grad, pupil_spectrum, workspace_size)
 
 __all__ = ["BpmError", "lib", "propagate", "propagate_batch", "adjoint", "fft2", "pupil_spectrum",
-           "pupil_phase_grad", "BPMFunction", "PupilBPMFunction", "workspace_size"]
+           "pupil_phase_grad", "psf_readout", "BPMFunction", "PupilBPMFunction", "workspace_size"]

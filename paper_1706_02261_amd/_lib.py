@@ -26,6 +26,7 @@ EXPORTS = (
     "bpm_propagate_batch", "bpm_adjoint_workspace_size", "bpm_adjoint",
     "psf_surrogate_infer", "bpm_error_string", "bpm_last_error",
     "bpm_fft2_workspace_size", "bpm_fft2", "bpm_pupil_spectrum", "bpm_pupil_phase_grad",
+    "bpm_psf_readout_workspace_size", "bpm_psf_readout",
 )
 
 
@@ -72,6 +73,11 @@ def _declare(L):
     L.bpm_pupil_spectrum.restype = _I
     L.bpm_pupil_phase_grad.argtypes = [_V, _V, _I, _I, _V, _V]
     L.bpm_pupil_phase_grad.restype = _I
+    L.bpm_psf_readout_workspace_size.argtypes = [_I, _I, _I]
+    L.bpm_psf_readout_workspace_size.restype = _Z
+    L.bpm_psf_readout.argtypes = [_V, _I, _I, _D, _D, _D, _D, _D, _I, _V, _I, _I, _I, _D, _V,
+                                  _V, _Z, _V]
+    L.bpm_psf_readout.restype = _I
     L.bpm_error_string.argtypes = [_I]
     L.bpm_error_string.restype = _S
     L.bpm_last_error.argtypes = []

@@ -256,3 +256,27 @@ def propagate_batch(jobs, ws: torch.Tensor | None = None, stream=None):
     rc = lib().bpm_propagate_batch(arr, len(jobs), _ptr(ws), ws.numel(), _stream_ptr(stream))
     check(rc, "bpm_propagate_batch")
     return results
+
+
+def psf_readout(exit_field: torch.Tensor, sources: torch.Tensor, dx: float, dz: float,
+                wavelength: float, n0: float, na: float, back_steps: int, planes: int = 32,
+                crop: int = 32, scale: float = 1.0, ws: torch.Tensor | None = None, stream=None):
+    """Refocused PSF stacks [n_src][planes][crop][crop] of a multiplexed run.
+
+    ``sources``: int32 [n_src][2] (y, x) pixel positions on the device."""
+    _need(exit_field, "exit_field", torch.complex64)
+    ny, nx = exit_field.shape
+    _need(sources, "sources", torch.int32)
+    if sources.dim() != 2 or sources.shape[1] != 2:
+        raise ValueError("sources must be [n_src][2]")
+    n_src = sources.shape[0]
+    out = torch.empty((n_src, planes, crop, crop), dtype=torch.float32, device=exit_field.device)
+    need = lib().bpm_psf_readout_workspace_size(nx, ny, planes)
+    if ws is None:
+        ws = workspace(need, exit_field.device)
+    rc = lib().bpm_psf_readout(_ptr(exit_field), nx, ny, float(dx), float(dz), float(wavelength),
+                               float(n0), float(na), int(back_steps), _ptr(sources), n_src,
+                               planes, crop, float(scale), _ptr(out), _ptr(ws), ws.numel(),
+                               _stream_ptr(stream))
+    check(rc, "bpm_psf_readout")
+    return out

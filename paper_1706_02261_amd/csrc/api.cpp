@@ -395,6 +395,37 @@ int bpm_pupil_phase_grad(const bpm_c64* grad_spectrum, const bpm_c64* spectrum, 
                          "pupil phase gradient");
 }
 
+size_t bpm_psf_readout_workspace_size(int nx, int ny, int planes) {
+    if (!pow2_in_range(nx) || !pow2_in_range(ny) || planes < 1 || planes > 256) return 0;
+    return bpm::readout_bytes(nx, ny, planes);
+}
+
+int bpm_psf_readout(const bpm_c64* exit_field, int nx, int ny, double dx, double dz,
+                    double wavelength, double n0, double na, int back_steps, const int* sources,
+                    int n_src, int planes, int crop, double scale, float* psf_out,
+                    void* workspace, size_t workspace_bytes, void* hip_stream) {
+    int rc = check_geom(nx, ny, 0, dx, dz, wavelength, n0);
+    if (rc) return rc;
+    if (!std::isfinite(na) || !(na > 0) || !std::isfinite(scale))
+        return fail(BPM_ERR_NOT_FINITE, "na=%g must be > 0 and scale finite", na);
+    if (back_steps < 0 || n_src < 0 || planes < 1 || planes > 256 || crop < 1 ||
+        crop > nx || crop > ny)
+        return fail(BPM_ERR_INVALID_ARG,
+                    "back_steps=%d, n_src=%d, planes=%d (1..256), crop=%d (1..min(nx, ny))",
+                    back_steps, n_src, planes, crop);
+    if (!exit_field || (n_src > 0 && (!sources || !psf_out)))
+        return fail(BPM_ERR_INVALID_ARG, "exit_field, sources and psf_out must be non-null");
+    if (!aligned(exit_field, 8) || (sources && !aligned(sources, 4)) ||
+        (psf_out && !aligned(psf_out, 4)))
+        return fail(BPM_ERR_INVALID_ARG, "misaligned array");
+    if ((rc = check_workspace(workspace, workspace_bytes, bpm::readout_bytes(nx, ny, planes))))
+        return rc;
+    const bpm::ReadoutArgs r{exit_field, nx, ny, dx, dz, wavelength, n0, na, back_steps, sources,
+                             n_src, planes, crop, scale, psf_out};
+    return device_status(bpm::launch_readout(r, workspace, static_cast<hipStream_t>(hip_stream)),
+                         "psf readout");
+}
+
 int psf_surrogate_infer(const void* weights_bf16, size_t weights_bytes, const float* dn_patches,
                         const float* depth, int batch, float* psf_out, float* pred_err,
                         void* hip_stream) {

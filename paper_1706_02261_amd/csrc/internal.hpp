@@ -84,6 +84,20 @@ int col_units(int nx, int ny);
 hipError_t launch_batch(const BatchJob* jobs_dev, const BatchSeg* segs_dev, int total,
                         unsigned* q, int n_jobs, hipStream_t s);
 
+// PSF readout of a multiplexed run (readout.hip).
+struct ReadoutArgs {
+    const void* exit_field;
+    int nx, ny;
+    double dx, dz, wavelength, n0, na;
+    int back_steps;
+    const int* sources;  // device [n_src][2] (y, x)
+    int n_src, planes, crop;
+    double scale;
+    float* psf_out;  // [n_src][planes][crop][crop]
+};
+size_t readout_bytes(int nx, int ny, int planes);
+hipError_t launch_readout(const ReadoutArgs& r, void* ws, hipStream_t s);
+
 // Pupil plane of the adaptive-optics gradient.
 hipError_t launch_pupil_spectrum(const float* amp, const float* phase, const Geom& g, double z_f,
                                  void* U, hipStream_t s);

@@ -19,6 +19,21 @@ constexpr int kBarWords = 1024;  // grid-barrier words (4 KiB) in the plan
 template <int N>
 constexpr int units_per_block() { return kBlock / (N / kR); }
 
+// calls f(std::integral_constant<int, n>{}) for a supported transform length n
+template <typename F>
+__host__ inline hipError_t dispatch_size(int n, F&& f) {
+    switch (n) {
+        case 32: return f(std::integral_constant<int, 32>{});
+        case 64: return f(std::integral_constant<int, 64>{});
+        case 128: return f(std::integral_constant<int, 128>{});
+        case 256: return f(std::integral_constant<int, 256>{});
+        case 512: return f(std::integral_constant<int, 512>{});
+        case 1024: return f(std::integral_constant<int, 1024>{});
+        case 2048: return f(std::integral_constant<int, 2048>{});
+        default: return hipErrorInvalidValue;
+    }
+}
+
 // The field travels between the passes of a persistent march through global
 // memory while the kernel runs.  The L2 caches of the eight XCDs are not
 // coherent with each other, so every access to a buffer written inside the
