@@ -40,13 +40,16 @@ PAPER_GVS = 1024 ** 3 / 0.5 / 1e9  # < 500 ms for 1024^3 voxels, main text
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "march_1024cube_traffic.json")
 
 
+MARCH_SOURCES = ("fft.hpp", "mathx.hpp", "passes.hpp", "march.hip")
+
+
 def kernel_source_hash() -> str:
+    """Hash of the sources the march kernel is compiled from."""
     h = hashlib.sha256()
     csrc = os.path.join(ROOT, "paper_1706_02261_amd", "csrc")
-    for name in sorted(os.listdir(csrc)):
-        if name.endswith((".hip", ".hpp")):
-            with open(os.path.join(csrc, name), "rb") as f:
-                h.update(name.encode() + b"\0" + f.read())
+    for name in MARCH_SOURCES:
+        with open(os.path.join(csrc, name), "rb") as f:
+            h.update(name.encode() + b"\0" + f.read())
     return h.hexdigest()[:16]
 
 

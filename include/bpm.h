@@ -195,18 +195,43 @@ int bpm_psf_readout(const bpm_c64* exit_field, int nx, int ny, double dx, double
                     int n_src, int planes, int crop, double scale, float* psf_out,
                     void* workspace, size_t workspace_bytes, void* hip_stream);
 
+/* Bytes of workspace for bpm_point_sources. */
+size_t bpm_point_sources_workspace_size(int nx, int ny);
+
+/* Multiplexed point-source input field (main-text paragraph on multiplexing:
+ * many point sources ride in one field and one march):
+ *   u0 = sum_i exp(i phase_i) shift(u_src, p_i)     (integer circular shifts)
+ *   u_src = IDFT2(S) / ||IDFT2(S)||_2,
+ *   S(k) = exp(-(kt / (k0 NA))^2) [kt <= k0 NA] exp(-i kz z_d),
+ * a Gaussian-apodised NA-limited point source whose focus lies z_d um after
+ * the input plane (z_d = 0: focused in the input plane), kz = sqrt(k^2 - kt^2),
+ * k = 2 pi n0 / wavelength, pupil by the integer test of bpm_psf_readout.
+ *   positions  device int32 [n_src][2] = (y, x) pixels (taken modulo ny, nx);
+ *   phases     device float32 [n_src] radians, or NULL for all zero;
+ *   field_out  device complex64 [ny][nx].
+ * n_src = 0 gives a zero field.  Coinciding positions add (float atomics, so
+ * the rounding of such sums does not depend on a fixed order). */
+int bpm_point_sources(const int* positions, const float* phases, int n_src, int nx, int ny,
+                      double dx, double wavelength, double n0, double na, double z_d,
+                      bpm_c64* field_out, void* workspace, size_t workspace_bytes,
+                      void* hip_stream);
+
 /* Learned PSF surrogate, inference (the paper's sets of 10^5 - 10^6 spatially
- * varying PSFs, abstract and main-text paragraph on image formation).
- *   weights_bf16   device blob written by the surrogate trainer (format in
- *                  the header at its start), weights_bytes its size.
+ * varying PSFs, abstract and main-text paragraph on image formation; the
+ * network and its training entries are in psf_surrogate.h).
+ *   weights_bf16   device blob written by psf_surrogate_export (256-byte
+ *                  aligned); weights_bytes must equal psf_surrogate_weights_bytes().
  *   dn_patches     [batch][64][32][32] float32 local dn patches (z, y, x).
  *   depth          [batch] float32 source depth in slices (0 .. 63).
- *   psf_out        [batch][32][32][32] float32 PSF intensity (z, y, x).
+ *   psf_out        [batch][32][32][32] float32 PSF intensity (plane, y, x).
  *   pred_err       [batch] float32 predicted relative L2 error of each PSF.
- * BF16 operands, FP32 accumulation on the matrix cores. */
+ *   workspace      psf_surrogate_workspace_size(batch, 0) bytes, 256-byte
+ *                  aligned; batches are processed in chunks of 256 samples.
+ * BF16 operands, FP32 accumulation on the matrix cores.  batch = 0 is a no-op. */
 int psf_surrogate_infer(const void* weights_bf16, size_t weights_bytes,
                         const float* dn_patches, const float* depth, int batch,
-                        float* psf_out, float* pred_err, void* hip_stream);
+                        float* psf_out, float* pred_err, void* workspace,
+                        size_t workspace_bytes, void* hip_stream);
 
 /* Static text for an error code. */
 const char* bpm_error_string(int code);

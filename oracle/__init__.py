@@ -18,6 +18,9 @@ Parity status of each function (what pins it, see tests/test_oracle_*.py):
 * conv3d_*        -- (surrogate) direct definition vs scipy correlate and
                      central finite differences.
 * psf_readout     -- free-space composition and dn = 0 focus.
+* point_sources   -- one source = numpy's inverse FFT of the closed-form
+                     spectrum, unit norm, shift and phase linearity.
+* surrogate_net   -- (module) central finite differences of the loss.
 """
 from __future__ import annotations
 
@@ -72,6 +75,9 @@ def _declare(L):
     L.oracle_psf_readout.argtypes = [_dp, _I, _I, _D, _D, _D, _D, _D, _I,
                                      ctypes.POINTER(ctypes.c_int), _I, _I, _I, _D, _dp]
     L.oracle_psf_readout.restype = _I
+    L.oracle_point_sources.argtypes = [ctypes.POINTER(ctypes.c_int), _dp, _I, _I, _I, _D, _D, _D,
+                                       _D, _D, _dp]
+    L.oracle_point_sources.restype = _I
     for name in ("oracle_set_threads", "oracle_fft1d", "oracle_fft2d", "oracle_propagator",
                  "oracle_bpm_forward", "oracle_bpm_adjoint"):
         getattr(L, name).restype = _I
@@ -212,6 +218,19 @@ def conv3d_backward(x, w, dy, stride=(1, 1, 1), pad=(1, 1, 1)):
     _check(lib().oracle_conv3d_backward(_ptr(x), _ptr(w), _ptr(dy), _ptr(dx), _ptr(dw), _ptr(db),
                                         *geo), "conv3d_backward")
     return dx, dw, db
+
+
+def point_sources(nx, ny, dx, wavelength, n0, na, z_d, positions, phases=None):
+    """Multiplexed point-source field [ny][nx] (complex128): the weighted sum of
+    integer circular shifts of one unit-norm NA-limited source."""
+    pos = np.ascontiguousarray(np.asarray(positions, dtype=np.int32).reshape(-1, 2))
+    ph = None if phases is None else _f64(phases)
+    out = np.empty((ny, nx), dtype=np.complex128)
+    rc = lib().oracle_point_sources(pos.ctypes.data_as(ctypes.POINTER(ctypes.c_int)), _ptr(ph),
+                                    len(pos), nx, ny, dx, wavelength, n0, na, z_d,
+                                    _ptr(out.view(np.float64)))
+    _check(rc, "point_sources")
+    return out
 
 
 def set_threads(n: int = 0) -> int:

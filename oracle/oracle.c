@@ -368,3 +368,68 @@ int oracle_psf_readout(const double *exit_field, int nx, int ny, double dx, doub
     free(S); free(E);
     return rc;
 }
+
+/* ------------------------------------------------------------------------ */
+/* multiplexed point-source input field                                     */
+/*
+ * Diffraction-limited point sources (main-text paragraphs on the detection
+ * PSFs and on multiplexing).  One source is the Gaussian-apodised,
+ * NA-limited angular spectrum
+ *
+ *   S(k) = exp(-(kt / (k0 NA))^2) [kt <= k0 NA] exp(-i kz z_d)
+ *
+ * (pupil by the integer test of the readout, kz = sqrt(k^2 - kt^2)), brought to
+ * real space by the inverse DFT and scaled to unit L2 norm:
+ * u_src = IDFT2(S) / ||IDFT2(S)||.  The multiplexed field is the weighted sum
+ * of its integer circular shifts, evaluated here by the direct double loop
+ *
+ *   u0[y][x] = sum_i exp(i phase_i) u_src[(y - py_i) mod ny][(x - px_i) mod nx].
+ *
+ * pos: (py, px) pixel pairs; phases may be NULL (all zero); out: [ny][nx].
+ */
+int oracle_point_sources(const int *pos, const double *phases, int n_src, int nx, int ny,
+                         double dx, double lam, double n0, double na, double z_d, double *out) {
+    if (!out || (n_src > 0 && !pos) || n_src < 0 || !is_pow2(nx) || !is_pow2(ny) || !(dx > 0) ||
+        !(lam > 0) || !(n0 > 0) || !(na > 0))
+        return ORACLE_ERR_ARG;
+    long n = (long)nx * ny;
+    cplx *src = (cplx *)malloc(sizeof(cplx) * (size_t)n);
+    if (!src) return ORACLE_ERR_MEM;
+    double k0 = 2.0 * PI / lam, k = n0 * k0, kmax = k0 * na;
+    double pthr = (double)nx * (double)ny * na * dx / lam;
+    pthr *= pthr;
+    for (int l = 0; l < ny; l++) {
+        double ky = 2.0 * PI * (double)signed_index(l, ny) / (ny * dx);
+        for (int m = 0; m < nx; m++) {
+            double kx = 2.0 * PI * (double)signed_index(m, nx) / (nx * dx);
+            double kt2 = kx * kx + ky * ky;
+            cplx v = 0.0;
+            if (prop_mask(m, l, nx, ny, pthr)) {
+                double kz = sqrt(fmax(k * k - kt2, 0.0));
+                v = exp(-kt2 / (kmax * kmax)) * (cos(kz * z_d) - I * sin(kz * z_d));
+            }
+            src[(long)l * nx + m] = v;
+        }
+    }
+    int rc = fft2d(src, nx, ny, +1);
+    if (rc) { free(src); return rc; }
+    double norm2 = 0.0;
+    for (long i = 0; i < n; i++) norm2 += creal(src[i]) * creal(src[i]) + cimag(src[i]) * cimag(src[i]);
+    double scale = 1.0 / sqrt(norm2);  /* the 1/(nx ny) of the IDFT cancels here */
+    cplx *u = (cplx *)out;
+    #pragma omp parallel for schedule(static)
+    for (int y = 0; y < ny; y++) {
+        for (int x = 0; x < nx; x++) {
+            cplx acc = 0.0;
+            for (int s = 0; s < n_src; s++) {
+                int sy = ((y - pos[2 * s]) % ny + ny) % ny;
+                int sx = ((x - pos[2 * s + 1]) % nx + nx) % nx;
+                double ph = phases ? phases[s] : 0.0;
+                acc += (cos(ph) + I * sin(ph)) * src[(long)sy * nx + sx];
+            }
+            u[(long)y * nx + x] = acc * scale;
+        }
+    }
+    free(src);
+    return 0;
+}

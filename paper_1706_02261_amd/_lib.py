@@ -1,4 +1,5 @@
-"""ctypes loader of libbpm.so and the declarations of include/bpm.h.
+"""ctypes loader of libbpm.so and the declarations of include/bpm.h and
+include/psf_surrogate.h.
 
 The library is the product path: when it is missing this module raises, and
 nothing falls back to another implementation.
@@ -20,13 +21,19 @@ BPM_ERR_NOT_FINITE = -5
 BPM_WS_FORWARD = 0
 BPM_WS_ADJOINT = 1
 
-# every symbol include/bpm.h declares
+# every symbol the headers under include/ declare
 EXPORTS = (
     "bpm_workspace_size", "bpm_propagate", "bpm_batch_workspace_size",
     "bpm_propagate_batch", "bpm_adjoint_workspace_size", "bpm_adjoint",
     "psf_surrogate_infer", "bpm_error_string", "bpm_last_error",
     "bpm_fft2_workspace_size", "bpm_fft2", "bpm_pupil_spectrum", "bpm_pupil_phase_grad",
     "bpm_psf_readout_workspace_size", "bpm_psf_readout",
+    "psf_surrogate_param_count", "psf_surrogate_weights_bytes", "psf_surrogate_state_bytes",
+    "psf_surrogate_workspace_size", "psf_surrogate_train_init", "psf_surrogate_train_step",
+    "psf_surrogate_gradients", "psf_surrogate_params", "psf_surrogate_export",
+    "psf_conv_workspace_size", "psf_conv_forward", "psf_conv_backward",
+    "psf_surrogate_layer_geometry", "psf_extract_patches",
+    "bpm_point_sources_workspace_size", "bpm_point_sources",
 )
 
 
@@ -47,6 +54,7 @@ class Job(ctypes.Structure):
 
 _lib = None
 _V, _I, _D, _Z, _S = ctypes.c_void_p, ctypes.c_int, ctypes.c_double, ctypes.c_size_t, ctypes.c_char_p
+_F = ctypes.c_float
 
 
 def _declare(L):
@@ -63,8 +71,35 @@ def _declare(L):
     L.bpm_adjoint.argtypes = [_V, _V, _I, _I, _I, _D, _D, _D, _D, _V, _V, _V, _V, _V, _I,
                               _V, _Z, _V]
     L.bpm_adjoint.restype = _I
-    L.psf_surrogate_infer.argtypes = [_V, _Z, _V, _V, _I, _V, _V, _V]
+    L.psf_surrogate_infer.argtypes = [_V, _Z, _V, _V, _I, _V, _V, _V, _Z, _V]
     L.psf_surrogate_infer.restype = _I
+    for name in ("psf_surrogate_param_count", "psf_surrogate_weights_bytes",
+                 "psf_surrogate_state_bytes"):
+        getattr(L, name).argtypes = []
+        getattr(L, name).restype = _Z
+    L.psf_surrogate_workspace_size.argtypes = [_I, _I]
+    L.psf_surrogate_workspace_size.restype = _Z
+    L.psf_surrogate_train_init.argtypes = [_V, _V, _V]
+    L.psf_surrogate_train_init.restype = _I
+    L.psf_surrogate_train_step.argtypes = [_V, _V, _V, _V, _I, _F, _F, _I, _V, _V, _V, _Z, _V]
+    L.psf_surrogate_train_step.restype = _I
+    for name in ("psf_surrogate_gradients", "psf_surrogate_params", "psf_surrogate_export"):
+        getattr(L, name).argtypes = [_V, _V, _V]
+        getattr(L, name).restype = _I
+    L.psf_extract_patches.argtypes = [_V, _I, _I, _I, _I, _V, _I, _V, _V]
+    L.psf_extract_patches.restype = _I
+    L.bpm_point_sources_workspace_size.argtypes = [_I, _I]
+    L.bpm_point_sources_workspace_size.restype = _Z
+    L.bpm_point_sources.argtypes = [_V, _V, _I, _I, _I, _D, _D, _D, _D, _D, _V, _V, _Z, _V]
+    L.bpm_point_sources.restype = _I
+    L.psf_surrogate_layer_geometry.argtypes = [_I, _V]
+    L.psf_surrogate_layer_geometry.restype = _I
+    L.psf_conv_workspace_size.argtypes = [_V]
+    L.psf_conv_workspace_size.restype = _Z
+    L.psf_conv_forward.argtypes = [_V, _V, _V, _V, _I, _V, _V, _V, _V, _Z, _V]
+    L.psf_conv_forward.restype = _I
+    L.psf_conv_backward.argtypes = [_V, _V, _V, _V, _V, _V, _V, _V, _V, _Z, _V]
+    L.psf_conv_backward.restype = _I
     L.bpm_fft2_workspace_size.argtypes = [_I, _I]
     L.bpm_fft2_workspace_size.restype = _Z
     L.bpm_fft2.argtypes = [_V, _V, _I, _I, _I, _V, _Z, _V]

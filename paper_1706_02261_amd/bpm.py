@@ -280,3 +280,31 @@ def psf_readout(exit_field: torch.Tensor, sources: torch.Tensor, dx: float, dz: 
                                _stream_ptr(stream))
     check(rc, "bpm_psf_readout")
     return out
+
+
+def point_sources(positions: torch.Tensor, nx: int, ny: int, dx: float, wavelength: float,
+                  n0: float, na: float, z_d: float = 0.0, phases: torch.Tensor | None = None,
+                  out: torch.Tensor | None = None, ws: torch.Tensor | None = None, stream=None):
+    """Multiplexed point-source field complex64 [ny][nx] (bpm_point_sources).
+
+    ``positions``: int32 [n][2] (y, x) on the device; ``phases``: float32 [n] or None."""
+    _need(positions, "positions", torch.int32)
+    if positions.dim() != 2 or positions.shape[1] != 2:
+        raise ValueError("positions must be [n][2]")
+    n = positions.shape[0]
+    if phases is not None:
+        _need(phases, "phases", torch.float32, (n,))
+    dev = positions.device
+    if out is None:
+        out = torch.empty((ny, nx), dtype=torch.complex64, device=dev)
+    _need(out, "out", torch.complex64, (ny, nx))
+    need = lib().bpm_point_sources_workspace_size(nx, ny)
+    if need == 0:
+        raise _lib.BpmError(_lib.BPM_ERR_UNSUPPORTED_SIZE, f"nx={nx} ny={ny}")
+    if ws is None:
+        ws = workspace(need, dev)
+    rc = lib().bpm_point_sources(_ptr(positions), _ptr(phases), n, nx, ny, float(dx),
+                                 float(wavelength), float(n0), float(na), float(z_d), _ptr(out),
+                                 _ptr(ws), ws.numel(), _stream_ptr(stream))
+    check(rc, "bpm_point_sources")
+    return out

@@ -12,26 +12,14 @@
 #include <vector>
 
 #include "../../include/bpm.h"
+#include "abi_util.hpp"
 #include "internal.hpp"
 
 namespace {
 
-thread_local std::string g_last_error;
-
-int fail(int code, const char* fmt, ...) __attribute__((format(printf, 2, 3)));
-int fail(int code, const char* fmt, ...) {
-    char buf[512];
-    va_list ap;
-    va_start(ap, fmt);
-    vsnprintf(buf, sizeof buf, fmt, ap);
-    va_end(ap);
-    g_last_error = buf;
-    return code;
-}
+using namespace bpm::abi;
 
 bool pow2_in_range(int n) { return n >= 32 && n <= 2048 && (n & (n - 1)) == 0; }
-
-bool aligned(const void* p, size_t a) { return (reinterpret_cast<uintptr_t>(p) % a) == 0; }
 
 // Shared validation of one march's scalar arguments.
 int check_geom(int nx, int ny, int steps, double dx, double dz, double wavelength, double n0) {
@@ -55,20 +43,6 @@ int check_field_ptrs(const void* in, const float* dn, int steps, const void* out
     if (!aligned(in, 8) || !aligned(out, 8) || (dn && !aligned(dn, 4)))
         return fail(BPM_ERR_INVALID_ARG, "fields must be 8-byte and dn 4-byte aligned");
     return BPM_OK;
-}
-
-int check_workspace(void* ws, size_t have, size_t need) {
-    if (!ws || have < need)
-        return fail(BPM_ERR_WORKSPACE, "workspace %p of %zu bytes; %zu bytes needed", ws, have,
-                    need);
-    if (!aligned(ws, bpm::kAlign))
-        return fail(BPM_ERR_WORKSPACE, "workspace must be %zu-byte aligned", bpm::kAlign);
-    return BPM_OK;
-}
-
-int device_status(hipError_t e, const char* what) {
-    if (e == hipSuccess) return BPM_OK;
-    return fail(BPM_ERR_DEVICE, "%s: %s", what, hipGetErrorString(e));
 }
 
 }  // namespace
@@ -426,12 +400,32 @@ int bpm_psf_readout(const bpm_c64* exit_field, int nx, int ny, double dx, double
                          "psf readout");
 }
 
-int psf_surrogate_infer(const void* weights_bf16, size_t weights_bytes, const float* dn_patches,
-                        const float* depth, int batch, float* psf_out, float* pred_err,
-                        void* hip_stream) {
-    (void)weights_bf16; (void)weights_bytes; (void)dn_patches; (void)depth; (void)batch;
-    (void)psf_out; (void)pred_err; (void)hip_stream;
-    return fail(BPM_ERR_INVALID_ARG, "psf_surrogate_infer: not built yet");
+size_t bpm_point_sources_workspace_size(int nx, int ny) {
+    if (!pow2_in_range(nx) || !pow2_in_range(ny)) return 0;
+    return bpm::sources_bytes(nx, ny);
+}
+
+int bpm_point_sources(const int* positions, const float* phases, int n_src, int nx, int ny,
+                      double dx, double wavelength, double n0, double na, double z_d,
+                      bpm_c64* field_out, void* workspace, size_t workspace_bytes,
+                      void* hip_stream) {
+    int rc = check_geom(nx, ny, 0, dx, 1.0, wavelength, n0);
+    if (rc) return rc;
+    if (!std::isfinite(na) || !std::isfinite(z_d) || !(na > 0))
+        return fail(BPM_ERR_NOT_FINITE, "na=%g must be finite and > 0, z_d=%g finite", na, z_d);
+    if (n_src < 0) return fail(BPM_ERR_INVALID_ARG, "n_src=%d must be >= 0", n_src);
+    if (n_src > 0 && (!positions || !aligned(positions, 4)))
+        return fail(BPM_ERR_INVALID_ARG, "positions must be non-null and 4-byte aligned");
+    if (phases && !aligned(phases, 4))
+        return fail(BPM_ERR_INVALID_ARG, "phases must be 4-byte aligned");
+    if (!field_out || !aligned(field_out, 8))
+        return fail(BPM_ERR_INVALID_ARG, "field_out must be non-null and 8-byte aligned");
+    if ((rc = check_workspace(workspace, workspace_bytes, bpm::sources_bytes(nx, ny)))) return rc;
+    const bpm::SourceArgs a{positions, phases, n_src, nx, ny, dx, wavelength, n0, na, z_d,
+                            field_out};
+    return device_status(
+        bpm::launch_point_sources(a, workspace, static_cast<hipStream_t>(hip_stream)),
+        "point sources");
 }
 
 }  // extern "C"

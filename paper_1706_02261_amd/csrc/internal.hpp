@@ -98,6 +98,54 @@ struct ReadoutArgs {
 size_t readout_bytes(int nx, int ny, int planes);
 hipError_t launch_readout(const ReadoutArgs& r, void* ws, hipStream_t s);
 
+// Multiplexed point-source input field (sources.hip).
+struct SourceArgs {
+    const int* positions;  // device [n_src][2] (y, x)
+    const float* phases;   // device [n_src] or nullptr (all zero)
+    int n_src, nx, ny;
+    double dx, wavelength, n0, na, z_d;
+    void* field_out;  // float2 [ny][nx]
+};
+size_t sources_bytes(int nx, int ny);
+hipError_t launch_point_sources(const SourceArgs& a, void* ws, hipStream_t s);
+
+// PSF surrogate kernels (surrogate.hip).  Activations are channels-last
+// bf16; a convolution's reduction index is (tap, channel), channel fastest.
+struct ConvGeo {
+    int N, D, H, W, Ci;           // input [N][D][H][W][Ci]
+    int Co, kd, kh, kw, sd, sh, sw, pd, ph, pw;
+    int Do, Ho, Wo;               // output [N][Do][Ho][Wo][Co]
+    int taps, K, Kp;              // taps = kd kh kw, K = taps Ci, Kp = K rounded up to 16
+};
+namespace sg {
+hipError_t conv_forward(const ConvGeo& c, const void* x, const void* w, const float* bias,
+                        const int4* taps, int epi, void* ybf, float* yf, float* zkeep,
+                        hipStream_t s);
+hipError_t conv_backward_data(const ConvGeo& c, const void* dy, const void* wt,
+                              const void* xact, const int4* taps_t, void* dx, hipStream_t s);
+hipError_t conv_backward_weight(const ConvGeo& c, const void* x, const void* dy,
+                                const int4* taps, float* dw, float* db, hipStream_t s);
+hipError_t prep_input(const float* dn, const float* depth, int B, void* x0, hipStream_t s);
+hipError_t extract_patches(const float* dn, int ny, int nx, int z0, const int* src, int n,
+                           float* out, hipStream_t s);
+hipError_t upsample(const void* a, int N, int h, int w, int C, void* u, hipStream_t s);
+hipError_t upsample_backward(const void* du, const void* a, const float* dpool, int N, int h,
+                             int w, int C, void* da, hipStream_t s);
+hipError_t head_forward(const void* a, int N, int hw, int C, const float* we, const float* be,
+                        float* pooled, float* epre, float* err, hipStream_t s);
+hipError_t loss_and_grad(const float* psf, const float* z, const float* target,
+                         const float* epre, const float* err, int B, float lambda, void* dy,
+                         float* derr_pre, float* loss, float* err_true, hipStream_t s);
+hipError_t head_backward(const float* pooled, const float* dpre, const float* we, int B, int C,
+                         float* dwe, float* dbe, float* dpool, hipStream_t s);
+hipError_t adam_update(float* w, const float* g, float* m, float* v, long n, float lr, int step,
+                       hipStream_t s);
+hipError_t pack_weights(const float* wf, int Co, int Ci, int taps, int Kp, void* wb, void* wt,
+                        hipStream_t s);
+hipError_t tap_tables(const ConvGeo& c, int4* taps, int4* taps_t, hipStream_t s);
+hipError_t fill_zero(float* p, long n, hipStream_t s);
+}  // namespace sg
+
 // Pupil plane of the adaptive-optics gradient.
 hipError_t launch_pupil_spectrum(const float* amp, const float* phase, const Geom& g, double z_f,
                                  void* U, hipStream_t s);

@@ -30,7 +30,7 @@ __all__ = [
     "smoothed_noise", "point_source_spectrum", "point_source_field",
     "multiplexed_field", "jittered_grid", "light_sheet_field", "Geometry",
     "config0", "config1", "config2_detection", "config2_light_sheet",
-    "config3", "batch_job_specs", "ellipsoid_phantom",
+    "config3", "batch_job_specs", "ellipsoid_phantom", "surrogate_volume",
 ]
 
 
@@ -367,6 +367,21 @@ def config3(steps: int | None = None, nxy: int = 256):
     amp = np.where(kt2 <= kmax ** 2, np.exp(-kt2 / kmax ** 2), 0.0)
     z_f = g.steps * g.dz
     return g, dn, amp, z_f
+
+
+def surrogate_volume(child: int, nxy: int = 1024, nz: int = 64) -> np.ndarray:
+    """A 64-slice volume of the PSF surrogate's data set (dx = dz = 0.2 um):
+    spheres of radius 1-4 um with dn in [0, 0.05] at the density of the
+    512^3 multiplexed-PSF workload (about 1000 per 1024^2 x 64 volume) plus
+    noise smoothed to 1 um with std 0.005, clipped to [0, 0.05]
+    (n 1.33-1.38).  ``child`` selects an independent volume."""
+    g = Geometry(nxy, nxy, nz, 0.2, 0.2)
+    n_sph = max(1, int(round(2000 * (nxy * nxy * nz) / 512 ** 3)))
+    dn = sphere_phantom(g, n_sph, (1.0, 4.0), (0.0, 0.05), rng(4, 2 * child))
+    dn += smoothed_noise(dn.shape, 1.0 / g.dx, 0.005, rng(4, 2 * child + 1),
+                         coarse=4 if dn.size > 64 ** 3 else 1)
+    np.clip(dn, 0.0, 0.05, out=dn)
+    return dn
 
 
 def batch_job_specs(n_jobs: int = 64, sizes=(256, 512, 1024), steps_range=(128, 1024),

@@ -1,11 +1,12 @@
 """C-ABI contract checks that need no GPU.
 
-The library loads on a host without a GPU, exports every function that
-include/bpm.h declares, and rejects bad arguments on the host before any HIP
+The library loads on a host without a GPU, exports every function that the
+headers under include/ declare, and rejects bad arguments on the host before any HIP
 call is made.  Pointers here are host addresses used only as non-null,
 aligned placeholders: every call below fails validation first.
 """
 import ctypes
+import glob
 import math
 import os
 import re
@@ -14,7 +15,7 @@ import numpy as np
 import pytest
 
 ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
-HEADER = os.path.join(ROOT, "include", "bpm.h")
+HEADERS = sorted(glob.glob(os.path.join(ROOT, "include", "*.h")))
 
 
 @pytest.fixture(scope="module")
@@ -24,9 +25,11 @@ def L():
 
 
 def declared_functions():
-    text = open(HEADER).read()
-    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
-    return sorted(set(re.findall(r"^\s*(?:const\s+)?\w+\*?\s+\**(\w+)\s*\(", text, flags=re.M)))
+    names = set()
+    for h in HEADERS:
+        text = re.sub(r"/\*.*?\*/", "", open(h).read(), flags=re.S)
+        names |= set(re.findall(r"^\s*(?:const\s+)?\w+\*?\s+\**(\w+)\s*\(", text, flags=re.M))
+    return sorted(names)
 
 
 def test_every_declared_symbol_is_exported(L):

@@ -1,0 +1,226 @@
+"""GPU parity of the surrogate's BF16 matrix-core kernels with the FP64 oracle.
+
+Convolutions (forward with both epilogues, data and weight gradients) are
+compared with the direct-loop oracle on the same bf16-rounded operands; the
+whole network's loss gradient and its inference output are compared with the
+FP64 network of oracle/surrogate_net.py, which rounds activations and
+gradient maps to bf16 where the network stores them in that format.
+
+Tolerances: a bf16 output carries one rounding (relative 2^-9) on top of an
+FP32 sum, so element-wise |gpu - ref| <= 2^-8 |ref| + 1e-4 max|ref|; FP32
+outputs (weight gradients, the softplus layer) stay within 1e-4 relative L2.
+Whole-network gradients differ where an FP32 sum lands on the other side of a
+bf16 rounding boundary than the FP64 one; 1e-2 relative L2 per parameter
+block bounds that.
+"""
+import numpy as np
+import pytest
+
+import oracle
+from oracle import surrogate_net as net
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+
+
+def rel(a, b):
+    return float(np.linalg.norm(np.ravel(a - b)) / max(np.linalg.norm(np.ravel(b)), 1e-300))
+
+
+def dims(geom):
+    from paper_1706_02261_amd import surrogate as S
+    return S.conv_dims(geom)
+
+
+def w_to_oracle(w, geom):
+    """[Co][Kp] fp32 (K ordered tap, channel) -> bf16-rounded [Co][Ci][kd][kh][kw] float64."""
+    Ci, Co, kd, kh, kw = geom[4], geom[5], geom[6], geom[7], geom[8]
+    K = kd * kh * kw * Ci
+    wb = w.to(torch.bfloat16).double().cpu().numpy()[:, :K]
+    return wb.reshape(Co, kd, kh, kw, Ci).transpose(0, 4, 1, 2, 3)
+
+
+def dw_from_oracle(dw, geom):
+    Co = geom[5]
+    Kp = dims(geom)[5]
+    flat = dw.transpose(0, 2, 3, 4, 1).reshape(Co, -1)
+    out = np.zeros((Co, Kp))
+    out[:, :flat.shape[1]] = flat
+    return out
+
+
+def x_to_oracle(x):
+    return x.double().cpu().numpy().transpose(0, 4, 1, 2, 3)
+
+
+def bf16_close(gpu, ref):
+    tol = 2.0 ** -8 * np.abs(ref) + 1e-4 * np.abs(ref).max()
+    bad = np.abs(gpu - ref) > tol
+    assert not bad.any(), f"{bad.sum()} of {bad.size} elements off, max {np.abs(gpu - ref).max()}"
+
+
+GEOMS = [
+    # N, D, H, W, Ci, Co, kd, kh, kw, sd, sh, sw, pd, ph, pw
+    (2, 8, 10, 9, 8, 32, 3, 3, 3, 2, 2, 2, 1, 1, 1),     # c1-like, K = 216 (ragged 16-chunk)
+    (2, 6, 7, 11, 32, 64, 3, 3, 3, 2, 1, 1, 1, 1, 1),    # strided, two Co tiles
+    (3, 4, 6, 6, 32, 64, 4, 3, 3, 1, 1, 1, 0, 1, 1),     # depth collapse
+    (2, 1, 12, 10, 64, 32, 1, 3, 3, 1, 1, 1, 0, 1, 1),   # 2-D decoder layer
+    (1, 64, 32, 32, 8, 32, 3, 3, 3, 2, 2, 2, 1, 1, 1),   # the network's first layer
+]
+
+
+def operands(geom, seed):
+    g = torch.Generator().manual_seed(seed)
+    N, D, H, W, Ci, Co = geom[:6]
+    Do, Ho, Wo, taps, K, Kp = dims(geom)
+    x = torch.randn(N, D, H, W, Ci, generator=g).to(torch.bfloat16)
+    w = torch.zeros(Co, Kp)
+    w[:, :K] = torch.randn(Co, K, generator=g) / np.sqrt(K)
+    b = torch.randn(Co, generator=g) * 0.1
+    dy = torch.randn(N, Do, Ho, Wo, Co, generator=g).to(torch.bfloat16)
+    return x.cuda(), w.cuda(), b.cuda(), dy.cuda()
+
+
+@pytest.mark.parametrize("geom", GEOMS)
+def test_conv_forward(geom):
+    from paper_1706_02261_amd import surrogate as S
+    x, w, b, _ = operands(geom, 1)
+    stride, pad = tuple(geom[9:12]), tuple(geom[12:15])
+    ref = oracle.conv3d_forward(x_to_oracle(x), w_to_oracle(w, geom), b.double().cpu().numpy(),
+                                stride=stride, pad=pad, relu=True)
+    y = S.conv_forward(x, w, b, geom, 0)
+    torch.cuda.synchronize()
+    bf16_close(y.double().cpu().numpy().transpose(0, 4, 1, 2, 3), ref)
+    if dims(geom)[0] == 1:
+        z_ref = oracle.conv3d_forward(x_to_oracle(x), w_to_oracle(w, geom),
+                                      b.double().cpu().numpy(), stride=stride, pad=pad)[:, :, 0]
+        yf, z = S.conv_forward(x, w, b, geom, 1)
+        torch.cuda.synchronize()
+        assert rel(z.double().cpu().numpy(), z_ref) <= 1e-5
+        assert rel(yf.double().cpu().numpy(), net.softplus(z_ref)) <= 1e-5
+
+
+@pytest.mark.parametrize("geom", GEOMS)
+def test_conv_backward(geom):
+    from paper_1706_02261_amd import surrogate as S
+    x, w, b, dy = operands(geom, 2)
+    stride, pad = tuple(geom[9:12]), tuple(geom[12:15])
+    dx_ref, dw_ref, db_ref = oracle.conv3d_backward(x_to_oracle(x), w_to_oracle(w, geom),
+                                                    x_to_oracle(dy), stride=stride, pad=pad)
+    want_dx = geom[4] % 32 == 0
+    mask = (torch.randn(x.shape, generator=torch.Generator().manual_seed(9)) > -0.3)
+    xmask = (mask.float() - 0.5).to(torch.bfloat16).cuda()
+    dx, dw, db = S.conv_backward(x, w, dy, geom, xmask=xmask if want_dx else None,
+                                 want_dx=want_dx)
+    torch.cuda.synchronize()
+    assert rel(dw.double().cpu().numpy(), dw_from_oracle(dw_ref, geom)) <= 1e-5
+    assert rel(db.double().cpu().numpy(), db_ref) <= 1e-5
+    if want_dx:
+        ref = dx_ref * mask.numpy().transpose(0, 4, 1, 2, 3)
+        bf16_close(dx.double().cpu().numpy().transpose(0, 4, 1, 2, 3), ref)
+
+
+def oracle_params(flat):
+    """The flat fp32 parameter vector as the FP64 network's weights (bf16 convs)."""
+    from paper_1706_02261_amd import surrogate as S
+    sl = S.param_slices()
+    p = {"w": [], "b": []}
+    for l in range(6):
+        g = S.layer_geometry(l)
+        w = flat[sl[("w", l)]].reshape(g[5], -1)
+        p["w"].append(w_to_oracle(w, g))
+        p["b"].append(flat[sl[("b", l)]].double().cpu().numpy())
+    p["we"] = flat[sl["we"]].double().cpu().numpy()
+    p["be"] = float(flat[sl["be"]].double().cpu().numpy()[0])
+    return p
+
+
+def grads_from_oracle(g):
+    from paper_1706_02261_amd import surrogate as S
+    sl = S.param_slices()
+    out = {}
+    for l in range(6):
+        out[("w", l)] = dw_from_oracle(g["w"][l], S.layer_geometry(l)).ravel()
+        out[("b", l)] = np.asarray(g["b"][l])
+    out["we"] = np.asarray(g["we"])
+    out["be"] = np.atleast_1d(g["be"])
+    return sl, out
+
+
+def batch(B, seed):
+    gen = np.random.default_rng(seed)
+    dn = gen.uniform(0, 0.05, (B, 64, 32, 32)).astype(np.float32)
+    depth = gen.integers(0, 64, B).astype(np.float32)
+    yy, xx = np.mgrid[:32, :32] - 15.5
+    target = np.stack([np.exp(-(yy ** 2 + xx ** 2) / (2 * (1.5 + 0.1 * abs(p - 16)) ** 2))
+                       for p in range(32)])[None].repeat(B, 0).astype(np.float32)
+    target *= (0.5 + depth / 64.0)[:, None, None, None].astype(np.float32)
+    return dn, depth, target
+
+
+def test_network_gradients():
+    from paper_1706_02261_amd import surrogate as S
+    params = S.init_params(seed=3)
+    params[S.param_slices()[("b", 5)]] = -1.0
+    params[S.param_slices()["we"]] *= 50.0
+    dn, depth, target = batch(2, 4)
+    lam = 0.5
+    model = S.PSFSurrogate("cuda", params)
+    dn_t, depth_t, tg_t = (torch.from_numpy(a).cuda() for a in (dn, depth, target))
+    err_true = torch.empty(2, device="cuda")
+    loss = model.train_step(dn_t, depth_t, tg_t, lr=0.0, err_weight=lam, err_true=err_true)
+    grads = model.gradients().double().cpu().numpy()
+    loss = loss.double().cpu().numpy()
+    p = oracle_params(params)
+    cache = net.forward(p, dn, depth, rnd=True)
+    l_psf, l_err, r = net.loss(cache, target, lam)
+    g = net.backward(p, cache, target, lam, rnd=True)
+    assert abs(loss[0] - l_psf) <= 1e-3 * l_psf
+    assert abs(loss[1] - l_err) <= 5e-3 * l_err + 1e-9
+    assert rel(err_true.double().cpu().numpy(), r) <= 1e-3
+    sl, ref = grads_from_oracle(g)
+    for key, s in sl.items():
+        assert rel(grads[s], ref[key]) <= 1e-2, key
+
+
+def test_inference_matches_oracle_and_is_batch_invariant():
+    from paper_1706_02261_amd import surrogate as S
+    params = S.init_params(seed=5)
+    params[S.param_slices()["we"]] *= 50.0
+    model = S.PSFSurrogate("cuda", params)
+    blob = model.export()
+    dn, depth, _ = batch(300, 6)
+    dn_t, depth_t = torch.from_numpy(dn).cuda(), torch.from_numpy(depth).cuda()
+    psf, err = S.infer(blob, dn_t, depth_t)          # two chunks: 256 + 44
+    psf_a, err_a = S.infer(blob, dn_t[290:].contiguous(), depth_t[290:].contiguous())
+    torch.cuda.synchronize()
+    assert torch.equal(psf[290:], psf_a) and torch.equal(err[290:], err_a)
+    p = oracle_params(params)
+    pick = [0, 255, 256, 299]
+    cache = net.forward(p, dn[pick], depth[pick], rnd=True)
+    assert rel(psf[pick].double().cpu().numpy(), cache["psf"]) <= 5e-3
+    assert rel(err[pick].double().cpu().numpy(), cache["err"]) <= 5e-3
+    # inference and the training forward agree
+    _, _, target = batch(4, 7)
+    e2 = torch.empty(4, device="cuda")
+    model.train_step(dn_t[:4].contiguous(), depth_t[:4].contiguous(),
+                     torch.from_numpy(target).cuda(), lr=0.0, err_true=e2)
+    psf4 = psf[:4].double().cpu().numpy()
+    r = np.sqrt(((psf4 - target) ** 2).sum(axis=(1, 2, 3)) / (target ** 2).sum(axis=(1, 2, 3)))
+    assert rel(e2.double().cpu().numpy(), r) <= 1e-5
+
+
+def test_training_reduces_loss():
+    from paper_1706_02261_amd import surrogate as S
+    model = S.PSFSurrogate("cuda", S.init_params(seed=8))
+    dn, depth, target = batch(16, 9)
+    dn_t, depth_t, tg_t = (torch.from_numpy(a).cuda() for a in (dn, depth, target))
+    first = model.train_step(dn_t, depth_t, tg_t, lr=0.0).clone()
+    for _ in range(100):
+        model.train_step(dn_t, depth_t, tg_t, lr=1e-3)
+    last = model.train_step(dn_t, depth_t, tg_t, lr=0.0)
+    torch.cuda.synchronize()
+    assert model.step_count == 100
+    assert float(last[0]) < 0.3 * float(first[0])
+    assert torch.isfinite(model.params()).all()
