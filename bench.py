@@ -89,6 +89,79 @@ def cpu_baseline(u0, dn_host, g, gpu_fn, target_s=15.0):
             "gpu_rel_l2_err_on_sample": err}
 
 
+SURROGATE_FLOP_PER_PSF = 2 * (8192 * 32 * 216 + 4096 * 32 * 864 + 2048 * 32 * 864
+                              + 1024 * 32 * 864 + 256 * 64 * 1152 + 1024 * 32 * 576)
+MFMA_BF16_PEAK_TFLOPS = 2500.0
+
+
+def psf_rates(dev, n_runs=8, n_infer=16384):
+    """PSFs/s of the BPM (multiplexed march + readout, 1024 sources per run at
+    depths spread over the 64-slice volume) and of the surrogate (patch
+    extraction + inference, error head included) on the same volume; the
+    surrogate's rate does not depend on its weights, so an untrained network
+    is timed."""
+    import numpy as np
+    import torch
+    import synth
+    from paper_1706_02261_amd import psfs
+    from paper_1706_02261_amd import surrogate as S
+    vol = torch.from_numpy(synth.surrogate_volume(3)).to(dev)
+    scale = 1.0 / psfs.reference_peak(1024, 1024, device=dev)
+    depths = [int(d) for d in np.linspace(2, 62, n_runs)]
+    stream = torch.cuda.current_stream(dev)
+
+    def bpm_all():
+        n = 0
+        for i, d in enumerate(depths):
+            _, _, t = psfs.training_run(vol, d, (i, 2 * i), 32, scale)
+            n += t.shape[0]
+        return n
+
+    bpm_all()
+    a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    torch.cuda.synchronize(dev)
+    a.record(stream)
+    n_bpm = bpm_all()
+    b.record(stream)
+    torch.cuda.synchronize(dev)
+    t_bpm = a.elapsed_time(b) / 1e3
+    gen = np.random.default_rng(5)
+    src = torch.from_numpy(np.stack([gen.integers(0, 1024, n_infer),
+                                     gen.integers(0, 1024, n_infer)], 1).astype(np.int32)).to(dev)
+    depth = torch.from_numpy(gen.integers(0, 64, n_infer).astype(np.float32)).to(dev)
+    blob = S.PSFSurrogate(dev, S.init_params(seed=1)).export()
+    out = torch.empty((n_infer,) + S.PSF, device=dev)
+    err = torch.empty(n_infer, device=dev)
+    patches = torch.empty((n_infer,) + S.PATCH, device=dev)
+    ws = S.workspace(max(int(S.lib().psf_surrogate_workspace_size(n_infer, 0)), 256), dev)
+
+    def infer():
+        S.extract_patches(vol, src, 0, out=patches)
+        S.infer(blob, patches, depth, psf_out=out, pred_err=err, ws=ws)
+
+    infer()
+    torch.cuda.synchronize(dev)
+    a.record(stream)
+    infer()
+    b.record(stream)
+    torch.cuda.synchronize(dev)
+    t_s = a.elapsed_time(b) / 1e3
+    tflops = SURROGATE_FLOP_PER_PSF * n_infer / t_s / 1e12
+    return {
+        "bpm_psfs_per_s": round(n_bpm / t_bpm, 1),
+        "bpm_sample": f"{n_runs} multiplexed runs of 1024 sources, 1024^2 x (64 - d) slices, "
+                      f"d in {depths[0]}..{depths[-1]}, 32-plane readout, 32^3 crops",
+        "surrogate_psfs_per_s": round(n_infer / t_s, 1),
+        "surrogate_sample": f"{n_infer} sources, patch extraction + BF16 inference with "
+                            "error head",
+        "surrogate_vs_bpm": round((n_infer / t_s) / (n_bpm / t_bpm), 4),
+        "surrogate_roofline": {"bound": "mfma", "achieved": round(tflops, 2),
+                               "peak": MFMA_BF16_PEAK_TFLOPS, "unit": "TFLOP/s",
+                               "frac": round(tflops / MFMA_BF16_PEAK_TFLOPS, 5),
+                               "flop_per_psf": SURROGATE_FLOP_PER_PSF},
+    }
+
+
 def main():
     ap = argparse.ArgumentParser(description=__doc__.split("\n\n")[0])
     ap.add_argument("--gpus", type=int, default=1)
@@ -96,6 +169,10 @@ def main():
     ap.add_argument("--warmup", type=int, default=2, help="untimed marches")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--slices", type=int, default=1024, help="march depth (default 1024)")
+    ap.add_argument("--no-psf", action="store_true", help="skip the surrogate vs BPM PSF rates")
+    ap.add_argument("--copy-mib", type=int, default=0,
+                    help="also run a plain device copy of this many MiB (the known-size "
+                         "kernel that scales rocprofv3's FETCH_SIZE / WRITE_SIZE counters)")
     args = ap.parse_args()
     world = int(os.environ.get("WORLD_SIZE", "1"))
     if args.gpus != 1 or world != 1:
@@ -144,7 +221,8 @@ def main():
     voxel_steps = g.nx * g.ny * g.steps
     value = voxel_steps / (ms / 1e3) / 1e9
     achieved = BYTES_PER_VOXEL_STEP * voxel_steps / (launch_ms / 1e3) / 1e9
-    traffic = measured_traffic()
+    traffic_bytes = measured_traffic()
+    traffic = None if traffic_bytes is None else round(traffic_bytes / (launch_ms / 1e3) / 1e9, 1)
     line = {
         "metric": METRIC,
         "value": round(value, 3),
@@ -172,6 +250,8 @@ def main():
             "unit": "GB/s",
             "frac": round(achieved / HBM_PEAK_GBS, 4),
             "traffic": traffic,
+            "traffic_bytes_per_voxel_step": None if traffic_bytes is None
+            else round(traffic_bytes / voxel_steps, 2),
             "kernel": "march_kernel (one launch per march, plan kernel included)",
             "launch_ms": round(launch_ms, 4),
             "bytes_per_voxel_step": BYTES_PER_VOXEL_STEP,
@@ -181,6 +261,14 @@ def main():
         },
         "input_generation_s": round(t_gen, 1),
     }
+    if args.copy_mib:
+        src = torch.ones(args.copy_mib * 2 ** 18, dtype=torch.float32, device=dev)
+        dst = torch.empty_like(src)
+        dst.copy_(src)
+        torch.cuda.synchronize(dev)
+        line["copy_calibration_bytes"] = src.numel() * 4
+    if not args.no_psf:
+        line["psf"] = psf_rates(dev)
     if not args.no_cpu_baseline:
         def gpu_first(steps):
             o, _ = bpm.propagate(field, dn[:steps].contiguous(), g.dx, g.dz, g.wavelength,

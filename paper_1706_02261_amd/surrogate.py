@@ -66,9 +66,11 @@ def param_slices():
     return out
 
 
-def init_params(seed: int = 0, out_bias: float = -2.0) -> torch.Tensor:
-    """He-normal conv weights (zero K padding), zero biases except the PSF
-    layer's (``out_bias``), small head weights; float32 on the CPU."""
+def init_params(seed: int = 0, out_bias: float = -4.5, hidden_bias: float = 0.05) -> torch.Tensor:
+    """He-normal conv weights (zero K padding), small positive biases of the
+    ReLU layers (``hidden_bias``, keeps units alive early in training), the PSF
+    layer's bias ``out_bias`` (softplus(-4.5) ~ 0.011, the order of a PSF
+    stack's mean), small head weights; float32 on the CPU."""
     gen = torch.Generator().manual_seed(seed)
     p = torch.zeros(param_count(), dtype=torch.float32)
     sl = param_slices()
@@ -83,6 +85,7 @@ def init_params(seed: int = 0, out_bias: float = -2.0) -> torch.Tensor:
             wk[:, :, IN_USED:] = 0.0
         w[:, :K] = wk.reshape(Co, K)
         p[sl[("w", l)]] = w.reshape(-1)
+        p[sl[("b", l)]] = hidden_bias
     p[sl[("b", N_LAYERS - 1)]] = out_bias
     p[sl["we"]] = torch.randn(HEAD_C, generator=gen) * 0.01
     p[sl["be"]] = -3.0

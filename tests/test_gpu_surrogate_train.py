@@ -30,6 +30,7 @@ torch = pytest.importorskip("torch")
 RUNS_PER_VOLUME = 12
 TRAIN_SECONDS = 75.0
 BATCH = 64
+LR = 1e-3
 
 
 def runs(vol, n_runs, gen, scale):
@@ -73,7 +74,9 @@ def trained():
         nb = Xtr.shape[0] // BATCH
         for b in range(nb):
             i = perm[b * BATCH:(b + 1) * BATCH]
-            lr = 1e-3 if epoch < 6 else 3e-4
+            step = epoch * nb + b
+            # linear warm-up over the first epoch, then a slow decay
+            lr = LR * min(1.0, (step + 1) / nb) / (1.0 + 0.05 * max(0, epoch - 1))
             total += model.train_step(Xtr[i].contiguous(), Dtr[i].contiguous(),
                                       Ttr[i].contiguous(), lr=lr, err_weight=1.0)
         torch.cuda.synchronize()
@@ -105,7 +108,8 @@ def test_surrogate_gain_over_invariant_psf(trained):
           flush=True)
     assert torch.isfinite(pred).all() and torch.isfinite(err).all()
     assert q(r_s, 0.5) < q(r_inv, 0.5)
-    assert q(r_s, 0.5) < 0.9 * q(r_inv, 0.5)
+    assert q(r_s, 0.95) < 0.7 * q(r_inv, 0.95)
+    assert corr > 0.5
 
 
 def test_fallback_is_the_bpm_readout(trained):
