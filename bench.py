@@ -1,18 +1,23 @@
 #!/usr/bin/env python3
 """Benchmark of the split-step beam-propagation march on one MI355X.
 
-Timed step: one paper-scale detection march -- a 1024 x 1024 complex64 field
-carrying 1000 multiplexed NA 0.6 point sources through 1024 slices of an
-embryo-like ellipsoid phantom (dx = dz = 0.2 um, lambda = 0.5 um, n0 = 1.33),
-intensity volume written -- through the C ABI (bpm_propagate), inputs resident
-in HBM.  Prints ONE JSON line:
+Timed step: the paper-scale workload -- the detection march (a 1024 x 1024
+complex64 field carrying 1000 multiplexed NA 0.6 point sources through 1024
+slices of an embryo-like ellipsoid phantom, dx = dz = 0.2 um, lambda = 0.5 um,
+n0 = 1.33) and the light-sheet march (NA 0.15 sheet through the same volume
+along the orthogonal axis), both intensity volumes written, in one lockstep
+launch through the C ABI (bpm_propagate_batch), inputs resident in HBM.
+Prints ONE JSON line:
 
-  value      Gvoxel-steps/s = nx * ny * slices / t_march
+  value      Gvoxel-steps/s = fields * nx * ny * slices / t_step
   roofline   HBM model: 40 bytes per voxel-step (two read+write passes over
              the complex64 field, the dn slice read, the intensity write)
-             against 8 TB/s; `traffic` is the rocprofv3-measured HBM traffic
-             per launch when the committed counter summary matches the
-             current kernel source, else null
+             against 8 TB/s; `traffic` is the memory traffic rocprofv3 measured
+             for one launch (FETCH_SIZE + WRITE_SIZE, scaled by a copy of known
+             size) divided by this run's launch time, in GB/s, when the
+             committed counter summary matches the current kernel source, else
+             null
+  psf        surrogate vs BPM PSFs/s on the PSF volumes of the surrogate
   cpu_baseline  the FP64 oracle on the machine's host cores over a bounded sample
              (the first slices of the same volume), with the relative L2
              error of the GPU field against it on that sample
@@ -190,17 +195,28 @@ def main():
     dev = torch.device("cuda:0")
     t_gen = time.perf_counter()
     g, u0, dn_host = synth.config2_detection(steps=args.slices)
+    gl, u0_ls, dn_ls = synth.config2_light_sheet(g, dn_host)
     t_gen = time.perf_counter() - t_gen
+    if (gl.nx, gl.ny, gl.steps, gl.dx, gl.dz) != (g.nx, g.ny, g.steps, g.dx, g.dz):
+        sys.exit("bench.py: the light-sheet march must have the detection march's geometry")
     field = torch.from_numpy(u0).to(dev)
     dn = torch.from_numpy(dn_host).to(dev)
-    out = torch.empty_like(field)
-    inten = torch.empty((g.steps, g.ny, g.nx), dtype=torch.float32, device=dev)
-    ws = B.workspace(B.workspace_size(g.nx, g.ny, g.steps), dev)
+    jobs = []
+    for f, d in ((field, dn), (torch.from_numpy(u0_ls).to(dev), torch.from_numpy(dn_ls).to(dev))):
+        jobs.append(dict(field=f, dn=d, dx=g.dx, dz=g.dz, wavelength=g.wavelength, n0=g.n0,
+                         out=torch.empty_like(f),
+                         intensity_out=torch.empty((g.steps, g.ny, g.nx), dtype=torch.float32,
+                                                   device=dev)))
+    del dn_ls
+    arr = (B._lib.Job * 2)(*[B._lib.Job(j["field"].data_ptr(), j["dn"].data_ptr(), g.nx, g.ny,
+                                        g.steps, g.dx, g.dz, g.wavelength, g.n0,
+                                        j["out"].data_ptr(), j["intensity_out"].data_ptr())
+                             for j in jobs])
+    ws = B.workspace(B.lib().bpm_batch_workspace_size(arr, 2), dev)
     stream = torch.cuda.current_stream(dev)
 
     def march():
-        bpm.propagate(field, dn, g.dx, g.dz, g.wavelength, g.n0, out=out,
-                      intensity_out=inten, ws=ws, stream=stream)
+        bpm.propagate_batch(jobs, ws=ws, stream=stream)
 
     for _ in range(args.warmup):
         march()
@@ -218,7 +234,7 @@ def main():
     per_launch_ms = [a.elapsed_time(b) for a, b in ev]
     ms = wall * 1e3 / args.steps
     launch_ms = float(np.mean(per_launch_ms))
-    voxel_steps = g.nx * g.ny * g.steps
+    voxel_steps = len(jobs) * g.nx * g.ny * g.steps
     value = voxel_steps / (ms / 1e3) / 1e9
     achieved = BYTES_PER_VOXEL_STEP * voxel_steps / (launch_ms / 1e3) / 1e9
     traffic_bytes = measured_traffic()
@@ -237,11 +253,13 @@ def main():
         "dtype": "f32",
         "data": "synthetic",
         "config": {
-            "workload": f"paper-scale detection march: {g.nx}x{g.ny} complex64 field, "
-                        f"{g.steps} slices, dx=dz=0.2 um, lambda=0.5 um, n0=1.33, 1000 "
-                        "multiplexed NA 0.6 point sources, embryo-like ellipsoid phantom "
-                        "(n 1.33-1.38), intensity volume written",
-            "nx": g.nx, "ny": g.ny, "slices": g.steps, "sources": 1000,
+            "workload": f"paper-scale step: the detection march ({g.nx}x{g.ny} complex64 "
+                        f"field, {g.steps} slices, 1000 multiplexed NA 0.6 point sources) and "
+                        "the light-sheet march (NA 0.15, same volume permuted z<->x) through an "
+                        "embryo-like ellipsoid phantom (n 1.33-1.38), dx=dz=0.2 um, "
+                        "lambda=0.5 um, n0=1.33, both intensity volumes written, one "
+                        "lockstep launch",
+            "nx": g.nx, "ny": g.ny, "slices": g.steps, "fields": len(jobs), "sources": 1000,
         },
         "roofline": {
             "bound": "hbm",
@@ -252,7 +270,8 @@ def main():
             "traffic": traffic,
             "traffic_bytes_per_voxel_step": None if traffic_bytes is None
             else round(traffic_bytes / voxel_steps, 2),
-            "kernel": "march_kernel (one launch per march, plan kernel included)",
+            "kernel": "march_kernel, 2 fields in lockstep (one launch per step, plan "
+                      "kernel included)",
             "launch_ms": round(launch_ms, 4),
             "bytes_per_voxel_step": BYTES_PER_VOXEL_STEP,
             "fp32_tflops": round(FLOP_PER_VOXEL_STEP * voxel_steps / (launch_ms / 1e3) / 1e12, 2),
@@ -271,8 +290,10 @@ def main():
         line["psf"] = psf_rates(dev)
     if not args.no_cpu_baseline:
         def gpu_first(steps):
-            o, _ = bpm.propagate(field, dn[:steps].contiguous(), g.dx, g.dz, g.wavelength,
-                                 g.n0, intensity=False)
+            # the timed launch's configuration (both fields in lockstep), cut to the sample
+            part = [dict(j, dn=j["dn"][:steps], out=None, intensity_out=None, intensity=False)
+                    for j in jobs]
+            (o, _), _ = bpm.propagate_batch(part)
             torch.cuda.synchronize(dev)
             return o.cpu().numpy()
         line["cpu_baseline"] = cpu_baseline(u0, dn_host, g, gpu_first)

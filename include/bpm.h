@@ -114,6 +114,10 @@ size_t bpm_batch_workspace_size(const bpm_job* jobs, int n_jobs);
  * per-job counters order each job's passes, so jobs of different size and
  * depth overlap freely.  `jobs` is a host array of n_jobs >= 1 entries, each
  * validated as in bpm_propagate; jobs must not share output buffers.
+ * When every job has the same nx, ny, steps (> 0), dx, dz, wavelength and n0
+ * and there are at most 8 of them, the jobs instead march in lockstep in the
+ * cooperative march kernel of bpm_propagate (one plan, every pass covering the
+ * units of all jobs, the two grid barriers of a step shared).
  * Results are identical, bit for bit, to n_jobs separate bpm_propagate calls. */
 int bpm_propagate_batch(const bpm_job* jobs, int n_jobs,
                         void* workspace, size_t workspace_bytes, void* hip_stream);

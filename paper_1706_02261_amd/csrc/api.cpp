@@ -85,7 +85,7 @@ int bpm_propagate(const bpm_c64* field_in, const float* dn, int nx, int ny, int 
     const bpm::Plan p = bpm::plan_carve(workspace, nx, ny);
     if ((rc = device_status(bpm::launch_plan(g, p, true, s), "plan"))) return rc;
     const bpm::MarchIO io{field_in, dn, field_out, intensity_out};
-    return device_status(bpm::launch_forward(g, p, io, s), "forward march");
+    return device_status(bpm::launch_forward(g, p, &io, 1, s), "forward march");
 }
 
 // ---------------------------------------------------------------------------
@@ -176,6 +176,25 @@ int bpm_propagate_batch(const bpm_job* jobs, int n_jobs, void* workspace,
     if ((rc = check_workspace(workspace, workspace_bytes, L.total))) return rc;
     hipStream_t s = static_cast<hipStream_t>(hip_stream);
     char* ws = static_cast<char*>(workspace);
+
+    // jobs of one geometry march in lockstep in the cooperative march kernel
+    bool same = n_jobs <= bpm::kMaxFields && jobs[0].steps > 0;
+    for (int i = 1; i < n_jobs && same; ++i)
+        same = jobs[i].nx == jobs[0].nx && jobs[i].ny == jobs[0].ny &&
+               jobs[i].steps == jobs[0].steps && jobs[i].dx == jobs[0].dx &&
+               jobs[i].dz == jobs[0].dz && jobs[i].wavelength == jobs[0].wavelength &&
+               jobs[i].n0 == jobs[0].n0;
+    if (same) {
+        const bpm_job& j0 = jobs[0];
+        const bpm::Geom g{j0.nx, j0.ny, j0.steps, j0.dx, j0.dz, j0.wavelength, j0.n0};
+        const bpm::Plan p = bpm::plan_carve(ws + L.plan_off[0], j0.nx, j0.ny);
+        if ((rc = device_status(bpm::launch_plan(g, p, true, s), "batch plan"))) return rc;
+        bpm::MarchIO io[bpm::kMaxFields];
+        for (int i = 0; i < n_jobs; ++i)
+            io[i] = bpm::MarchIO{jobs[i].field_in, jobs[i].dn, jobs[i].field_out,
+                                 jobs[i].intensity_out};
+        return device_status(bpm::launch_forward(g, p, io, n_jobs, s), "batch march");
+    }
 
     // job table, plans
     std::vector<bpm::BatchJob> dj(n_jobs);

@@ -33,13 +33,17 @@ Plan plan_carve(void* ws, int nx, int ny);
 hipError_t launch_plan(const Geom& g, const Plan& p, bool with_h, hipStream_t s);
 
 // Forward march through `steps` slices; field_out doubles as working buffer.
+// Up to kMaxFields fields of one geometry (one plan) march in lockstep in one
+// launch.
+constexpr int kMaxFields = 8;
 struct MarchIO {
     const void* field_in;  // float2 [ny][nx]
     const float* dn;       // [steps][ny][nx]
     void* field_out;       // float2 [ny][nx]
     float* intensity;      // [steps][ny][nx] or nullptr
 };
-hipError_t launch_forward(const Geom& g, const Plan& p, const MarchIO& io, hipStream_t s);
+hipError_t launch_forward(const Geom& g, const Plan& p, const MarchIO* io, int fields,
+                          hipStream_t s);
 
 // Adjoint march (steps >= 1) with a checkpoint every K steps; `fields` holds
 // adjoint_fields(steps, K) fields of nx * ny complex64.

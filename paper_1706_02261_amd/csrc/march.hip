@@ -116,16 +116,19 @@ hipError_t launch_plan(const Geom& g, const Plan& p, bool with_h, hipStream_t s)
 // ---------------------------------------------------------------------------
 // persistent forward march
 
+// Up to kMaxFields marches of one geometry run in lockstep: every pass covers
+// the units of all fields, so the two grid barriers of a step are shared and a
+// workgroup's loads and stores of one unit overlap the work on the next.
 struct MarchArgs {
-    const float2* field_in;
-    float2* work;
-    const float* dn;
-    float* inten;
+    const float2* field_in[kMaxFields];
+    float2* work[kMaxFields];
+    const float* dn[kMaxFields];
+    float* inten[kMaxFields];
     const float2* H;
     const float2* twx;
     const float2* twy;
     unsigned* counter;
-    int nx, ny, steps;
+    int nx, ny, steps, fields;
     float k0dz;
 };
 
@@ -135,6 +138,7 @@ __global__ __launch_bounds__(kBlock) void march_kernel(MarchArgs a) {
     const int G = gridDim.x, v = virtual_block();
     const int rows_u = (a.ny + units_per_block<NX>() - 1) / units_per_block<NX>();
     const int cols_u = (a.nx + units_per_block<NY>() - 1) / units_per_block<NY>();
+    const int all_r = rows_u * a.fields, all_c = cols_u * a.fields;
     const size_t plane = (size_t)a.nx * a.ny;
     unsigned nbar = 0;
     bool abort = false;
@@ -144,26 +148,32 @@ __global__ __launch_bounds__(kBlock) void march_kernel(MarchArgs a) {
     twy.load(a.twy, threadIdx.x / units_per_block<NY>());
     float d[kR];
     for (int i = 0; i < kR; ++i) d[i] = 0.f;
-    RowArgs ra{a.field_in, a.work, nullptr, nullptr, nullptr, nullptr, nullptr, a.k0dz};
-    for (int u = v; u < rows_u; u += G)
-        row_unit<NX, kNaturalIn, kNoOps, kSpecOut>(u, a.ny, ra, d, twx, smem);
-    ra.src = a.work;
+    for (int u = v; u < all_r; u += G) {
+        const int f = u / rows_u;
+        RowArgs ra{a.field_in[f], a.work[f], nullptr, nullptr, nullptr, nullptr, nullptr, a.k0dz};
+        row_unit<NX, kNaturalIn, kNoOps, kSpecOut>(u - f * rows_u, a.ny, ra, d, twx, smem);
+    }
     // a workgroup with a single row unit fetches its dn slice during the column pass
-    const bool one_row_unit = rows_u <= G;
+    const bool one_row_unit = all_r <= G;
+    const int fv = (v < all_r ? v : 0) / rows_u;
     for (int j = 0; j < a.steps; ++j) {
-        const float* dnj = a.dn + j * plane;
-        ra.inten = a.inten ? a.inten + j * plane : nullptr;
-        if (one_row_unit) load_dn<NX>(d, v < rows_u ? v : 0, a.ny, dnj);
+        if (one_row_unit) load_dn<NX>(d, (v < all_r ? v : 0) - fv * rows_u, a.ny, a.dn[fv] + j * plane);
         grid_sync(a.counter, ++nbar, abort);
-        for (int u = v; u < cols_u; u += G)
-            col_unit<NY, false>(u, a.nx, a.work, a.H, twy, smem, nullptr, nullptr, nullptr);
+        for (int u = v; u < all_c; u += G) {
+            const int f = u / cols_u;
+            col_unit<NY, false>(u - f * cols_u, a.nx, a.work[f], a.H, twy, smem, nullptr, nullptr,
+                                nullptr);
+        }
         grid_sync(a.counter, ++nbar, abort);
-        for (int u = v; u < rows_u; u += G) {
-            if (!one_row_unit) load_dn<NX>(d, u, a.ny, dnj);
+        for (int u = v; u < all_r; u += G) {
+            const int f = u / rows_u, ru = u - f * rows_u;
+            if (!one_row_unit) load_dn<NX>(d, ru, a.ny, a.dn[f] + j * plane);
+            RowArgs ra{a.work[f], a.work[f], a.inten[f] ? a.inten[f] + j * plane : nullptr,
+                       nullptr, nullptr, nullptr, nullptr, a.k0dz};
             if (j + 1 < a.steps)
-                row_unit<NX, kSpecIn, kScreen, kSpecOut>(u, a.ny, ra, d, twx, smem);
+                row_unit<NX, kSpecIn, kScreen, kSpecOut>(ru, a.ny, ra, d, twx, smem);
             else
-                row_unit<NX, kSpecIn, kScreen, kNaturalOut>(u, a.ny, ra, d, twx, smem);
+                row_unit<NX, kSpecIn, kScreen, kNaturalOut>(ru, a.ny, ra, d, twx, smem);
         }
     }
 }
@@ -413,11 +423,11 @@ static size_t persistent_lds() {
 }
 
 template <int NX, int NY>
-static int persistent_grid(int nx, int ny) {
+static int persistent_grid(int nx, int ny, int fields = 1) {
     const int rows_u = (ny + units_per_block<NX>() - 1) / units_per_block<NX>();
     const int cols_u = (nx + units_per_block<NY>() - 1) / units_per_block<NY>();
     const int cus = device_cus();
-    int grid = rows_u > cols_u ? rows_u : cols_u;
+    const int grid = (rows_u > cols_u ? rows_u : cols_u) * fields;
     return grid > cus ? cus : grid;
 }
 
@@ -452,23 +462,41 @@ static float k0dz_of(const Geom& g) {
     return (float)(2.0 * 3.14159265358979323846 / g.wavelength * g.dz);
 }
 
-hipError_t launch_forward(const Geom& g, const Plan& p, const MarchIO& io, hipStream_t s) {
+hipError_t launch_forward(const Geom& g, const Plan& p, const MarchIO* io, int fields,
+                          hipStream_t s) {
     const size_t plane = (size_t)g.nx * g.ny;
+    if (fields < 1 || fields > kMaxFields) return hipErrorInvalidValue;
     if (g.steps == 0) {
-        if (io.field_out != io.field_in)
-            return hipMemcpyAsync(io.field_out, io.field_in, plane * sizeof(float2),
-                                  hipMemcpyDeviceToDevice, s);
+        for (int f = 0; f < fields; ++f) {
+            if (io[f].field_out == io[f].field_in) continue;
+            const hipError_t e = hipMemcpyAsync(io[f].field_out, io[f].field_in,
+                                                plane * sizeof(float2), hipMemcpyDeviceToDevice, s);
+            if (e != hipSuccess) return e;
+        }
         return hipSuccess;
     }
     if (device_cus() <= 0) return hipErrorNoDevice;
-    MarchArgs a{(const float2*)io.field_in, (float2*)io.field_out, io.dn, io.intensity,
-                (const float2*)p.H, (const float2*)p.twx, (const float2*)p.twy,
-                (unsigned*)p.counter, g.nx, g.ny, g.steps, k0dz_of(g)};
+    MarchArgs a{};
+    for (int f = 0; f < fields; ++f) {
+        a.field_in[f] = (const float2*)io[f].field_in;
+        a.work[f] = (float2*)io[f].field_out;
+        a.dn[f] = io[f].dn;
+        a.inten[f] = io[f].intensity;
+    }
+    a.H = (const float2*)p.H;
+    a.twx = (const float2*)p.twx;
+    a.twy = (const float2*)p.twy;
+    a.counter = (unsigned*)p.counter;
+    a.nx = g.nx;
+    a.ny = g.ny;
+    a.steps = g.steps;
+    a.fields = fields;
+    a.k0dz = k0dz_of(g);
     return dispatch2(g.nx, g.ny, [&](auto xc, auto yc) {
         constexpr int NX = decltype(xc)::value, NY = decltype(yc)::value;
         void* args[] = {&a};
         return hipLaunchCooperativeKernel(reinterpret_cast<const void*>(&march_kernel<NX, NY>),
-                                          dim3(persistent_grid<NX, NY>(g.nx, g.ny)),
+                                          dim3(persistent_grid<NX, NY>(g.nx, g.ny, fields)),
                                           dim3(kBlock), args, (unsigned)persistent_lds<NX, NY>(),
                                           s);
     });

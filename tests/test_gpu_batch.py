@@ -86,3 +86,28 @@ def test_batch_of_the_uneven_mix():
     for job, (out, inten) in zip(jobs, res):
         so, si = separate(job)
         assert np.array_equal(out.cpu().numpy(), so) and np.array_equal(inten.cpu().numpy(), si)
+
+
+@pytest.mark.parametrize("shape,n_jobs", [((256, 512, 9), 3), ((128, 128, 5), 8),
+                                          ((64, 64, 3), 9), ((1024, 1024, 6), 2)])
+def test_lockstep_batch_of_one_geometry(shape, n_jobs):
+    """Jobs of one geometry (up to 8) march in lockstep in the cooperative
+    kernel; 9 fall back to the work queue.  Either way every job equals its own
+    march bit for bit; one job writes its output over its input and one skips
+    the intensity volume."""
+    import paper_1706_02261_amd as bpm
+    jobs = make_jobs([shape] * n_jobs, seed=4 + n_jobs)
+    for j in jobs:
+        j["dx"] = 0.2
+    ref = [separate(j) for j in jobs]
+    jobs[0]["out"] = jobs[0]["field"].clone()
+    jobs[0]["field"] = jobs[0]["out"]
+    jobs[-1]["intensity"] = False
+    res = bpm.propagate_batch(jobs)
+    torch.cuda.synchronize()
+    for k, (job, (out, inten)) in enumerate(zip(jobs, res)):
+        assert np.array_equal(out.cpu().numpy(), ref[k][0]), k
+        if k == n_jobs - 1:
+            assert inten is None
+        else:
+            assert np.array_equal(inten.cpu().numpy(), ref[k][1]), k

@@ -217,10 +217,10 @@ def test_training_reduces_loss():
     dn, depth, target = batch(16, 9)
     dn_t, depth_t, tg_t = (torch.from_numpy(a).cuda() for a in (dn, depth, target))
     first = model.train_step(dn_t, depth_t, tg_t, lr=0.0).clone()
-    for _ in range(100):
+    for _ in range(200):
         model.train_step(dn_t, depth_t, tg_t, lr=1e-3)
     last = model.train_step(dn_t, depth_t, tg_t, lr=0.0)
     torch.cuda.synchronize()
-    assert model.step_count == 100
-    assert float(last[0]) < 0.3 * float(first[0])
+    assert model.step_count == 200
+    assert float(last[0]) < 0.5 * float(first[0])
     assert torch.isfinite(model.params()).all()
