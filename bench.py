@@ -167,6 +167,100 @@ def psf_rates(dev, n_runs=8, n_infer=16384):
     }
 
 
+ADJOINT_BYTES_PER_VOXEL_STEP = 128   # checkpoint march + segment recompute + adjoint, whole call
+
+
+def adjoint_rate(dev, reps=3):
+    """The adjoint workload: 256^2 x 512 sphere phantom, gradients of the
+    negative focal-spot intensity with respect to the pupil spectrum and dn
+    (sqrt(N) checkpoints), one bpm_adjoint call."""
+    import numpy as np
+    import torch
+    import synth
+    import paper_1706_02261_amd as bpm
+    g, dn_h, amp, z_f = synth.config3()
+    dn = torch.from_numpy(dn_h).to(dev)
+    phase = torch.zeros((g.ny, g.nx), dtype=torch.float32, device=dev)
+    U0 = bpm.pupil_spectrum(torch.from_numpy(amp.astype(np.float32)).to(dev), phase, g.dx,
+                            g.wavelength, g.n0, z_f)
+    u0 = bpm.fft2(U0, inverse=True)
+    gI = torch.zeros((g.steps, g.ny, g.nx), dtype=torch.float32, device=dev)
+    gI[-1, g.ny // 2, g.nx // 2] = -1.0
+    stream = torch.cuda.current_stream(dev)
+
+    def run():
+        return bpm.adjoint(u0, dn, g.dx, g.dz, g.wavelength, g.n0, grad_intensity=gI,
+                           want_field=False, want_spectrum=True, want_dn=True, stream=stream)
+
+    run()
+    torch.cuda.synchronize(dev)
+    ts = []
+    for _ in range(reps):
+        a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        a.record(stream)
+        run()
+        b.record(stream)
+        torch.cuda.synchronize(dev)
+        ts.append(a.elapsed_time(b))
+    ms = float(np.median(ts))
+    vs = g.nx * g.ny * g.steps
+    achieved = ADJOINT_BYTES_PER_VOXEL_STEP * vs / (ms / 1e3) / 1e9
+    return {"workload": f"adjoint {g.nx}x{g.ny}x{g.steps}, sqrt(N) checkpoints, gradients "
+                        "w.r.t. pupil spectrum and dn",
+            "ms": round(ms, 3), "gvoxel_steps_per_s": round(vs / (ms / 1e3) / 1e9, 3),
+            "roofline": {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,
+                         "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),
+                         "bytes_per_voxel_step": ADJOINT_BYTES_PER_VOXEL_STEP}}
+
+
+def batch_rate(dev):
+    """The uneven batch: 64 jobs, nx, ny in {256, 512, 1024}, 128-1024 steps,
+    dn + intensity <= 160 GiB, one work-queue launch.  dn is uniform random in
+    [0, 0.05] drawn on the device (the rate does not depend on its values)."""
+    import numpy as np
+    import torch
+    import synth
+    import paper_1706_02261_amd as bpm
+    from paper_1706_02261_amd import bpm as B
+    specs = synth.batch_job_specs()
+    gen = torch.Generator(device=dev).manual_seed(1002)
+    jobs = []
+    for nx, ny, steps in specs:
+        u0 = torch.randn((ny, nx), dtype=torch.complex64, device=dev, generator=gen)
+        dn = torch.rand((steps, ny, nx), dtype=torch.float32, device=dev, generator=gen) * 0.05
+        jobs.append(dict(field=u0, dn=dn, dx=0.2, dz=0.2, wavelength=0.5, n0=1.33,
+                         out=torch.empty_like(u0),
+                         intensity_out=torch.empty((steps, ny, nx), dtype=torch.float32,
+                                                   device=dev)))
+    arr = (B._lib.Job * len(jobs))(*[B._lib.Job(j["field"].data_ptr(), j["dn"].data_ptr(),
+                                                j["field"].shape[1], j["field"].shape[0],
+                                                j["dn"].shape[0], 0.2, 0.2, 0.5, 1.33,
+                                                j["out"].data_ptr(),
+                                                j["intensity_out"].data_ptr())
+                                     for j in jobs])
+    ws = B.workspace(B.lib().bpm_batch_workspace_size(arr, len(jobs)), dev)
+    stream = torch.cuda.current_stream(dev)
+    bpm.propagate_batch(jobs, ws=ws, stream=stream)
+    torch.cuda.synchronize(dev)
+    a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    a.record(stream)
+    bpm.propagate_batch(jobs, ws=ws, stream=stream)
+    b.record(stream)
+    torch.cuda.synchronize(dev)
+    ms = a.elapsed_time(b)
+    vs = sum(nx * ny * st for nx, ny, st in specs)
+    achieved = BYTES_PER_VOXEL_STEP * vs / (ms / 1e3) / 1e9
+    del jobs, ws
+    torch.cuda.empty_cache()
+    return {"workload": f"{len(specs)} uneven jobs (nx, ny in 256..1024, steps 128..1024), "
+                        "one persistent work-queue launch",
+            "voxel_steps": vs, "ms": round(ms, 2),
+            "gvoxel_steps_per_s": round(vs / (ms / 1e3) / 1e9, 3),
+            "roofline": {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,
+                         "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),
+                         "bytes_per_voxel_step": BYTES_PER_VOXEL_STEP}}
+
+
 def main():
     ap = argparse.ArgumentParser(description=__doc__.split("\n\n")[0])
     ap.add_argument("--gpus", type=int, default=1)
@@ -175,6 +269,8 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--slices", type=int, default=1024, help="march depth (default 1024)")
     ap.add_argument("--no-psf", action="store_true", help="skip the surrogate vs BPM PSF rates")
+    ap.add_argument("--no-extra", action="store_true",
+                    help="skip the adjoint and uneven-batch rates")
     ap.add_argument("--copy-mib", type=int, default=0,
                     help="also run a plain device copy of this many MiB (the known-size "
                          "kernel that scales rocprofv3's FETCH_SIZE / WRITE_SIZE counters)")
@@ -288,6 +384,9 @@ def main():
         line["copy_calibration_bytes"] = src.numel() * 4
     if not args.no_psf:
         line["psf"] = psf_rates(dev)
+    if not args.no_extra:
+        line["adjoint"] = adjoint_rate(dev)
+        line["uneven_batch"] = batch_rate(dev)
     if not args.no_cpu_baseline:
         def gpu_first(steps):
             # the timed launch's configuration (both fields in lockstep), cut to the sample

@@ -235,6 +235,22 @@ struct Twiddles {
             for (int m = 0; m < R; ++m) w[s][m] = m ? tw[(tp * m * step) & (N - 1)] : make_float2(1.f, 0.f);
         }
     }
+    __device__ __forceinline__ float2 get(int s, int m) const { return w[s][m]; }
+};
+
+// The same twiddles read on use from a table tw[e] = exp(-2 pi i e / N) in LDS
+// (one table per transform length, shared by the workgroup): no registers held
+// across the passes, one LDS read per twiddle.
+template <int N, int R>
+struct LdsTwiddles {
+    const float2* tab;
+    int tau;
+    __device__ __forceinline__ float2 get(int s, int m) const {
+        const int ta = fft_t_after(N, R, s);
+        const int tp = s == 0 ? tau : tau % ta;
+        const int step = N / (fft_radix(N, R, s) * ta);
+        return tab[(tp * m * step) & (N - 1)];
+    }
 };
 
 // ---------------------------------------------------------------------------
@@ -247,15 +263,15 @@ struct Twiddles {
 
 // Forward transform (exp(-...)).  In: v[i] = x[i*T + tau], natural order.
 // Out: v[reg] = X[fft_freq_of_pos(pos_of_reg(tau, reg))].
-template <int N, int R, int LSTRIDE, typename Sync>
-__device__ __forceinline__ void fft_forward(float2 (&v)[R], float2* lds, int tau,
-                                            const Twiddles<N, R>& tw, Sync sync) {
+template <int N, int R, int LSTRIDE, typename Tw, typename Sync>
+__device__ __forceinline__ void fft_forward(float2 (&v)[R], float2* lds, int tau, const Tw& tw,
+                                            Sync sync) {
     using L = FftLayout<N, R>;
     constexpr int T = L::T;
     dft_reg<R, -1>(v);
     if constexpr (L::S > 1) {
 #pragma unroll
-        for (int k = 1; k < R; ++k) v[k] = c_mul(v[k], tw.w[0][k]);
+        for (int k = 1; k < R; ++k) v[k] = c_mul(v[k], tw.get(0, k));
 #pragma unroll
         for (int k = 0; k < R; ++k) lds[lds_pad(k * T + tau) * LSTRIDE] = v[k];
         sync();
@@ -273,7 +289,7 @@ __device__ __forceinline__ void fft_forward(float2 (&v)[R], float2* lds, int tau
                 const int base = (tau / ta) * r * ta + tau % ta;  // one group per thread
 #pragma unroll
                 for (int m = 0; m < r; ++m) {
-                    const float2 z = m ? c_mul(v[m], tw.w[s][m]) : v[m];
+                    const float2 z = m ? c_mul(v[m], tw.get(s, m)) : v[m];
                     lds[lds_pad(base + m * ta) * LSTRIDE] = z;
                 }
                 sync();
@@ -284,9 +300,9 @@ __device__ __forceinline__ void fft_forward(float2 (&v)[R], float2* lds, int tau
 
 // Inverse transform (exp(+...), unnormalised): exact mirror of fft_forward.
 // In: the forward's output layout.  Out: v[i] = N * x[i*T + tau].
-template <int N, int R, int LSTRIDE, typename Sync>
-__device__ __forceinline__ void fft_inverse(float2 (&v)[R], float2* lds, int tau,
-                                            const Twiddles<N, R>& tw, Sync sync) {
+template <int N, int R, int LSTRIDE, typename Tw, typename Sync>
+__device__ __forceinline__ void fft_inverse(float2 (&v)[R], float2* lds, int tau, const Tw& tw,
+                                            Sync sync) {
     using L = FftLayout<N, R>;
     constexpr int T = L::T;
     if constexpr (L::S > 1) {
@@ -298,7 +314,7 @@ __device__ __forceinline__ void fft_inverse(float2 (&v)[R], float2* lds, int tau
 #pragma unroll
                 for (int m = 0; m < r; ++m) {
                     const float2 z = lds[lds_pad(base + m * ta) * LSTRIDE];
-                    v[m] = m ? c_mulc(z, tw.w[s][m]) : z;
+                    v[m] = m ? c_mulc(z, tw.get(s, m)) : z;
                 }
             }
             dft_groups<r, +1>(v);
@@ -313,7 +329,7 @@ __device__ __forceinline__ void fft_inverse(float2 (&v)[R], float2* lds, int tau
 #pragma unroll
         for (int k = 0; k < R; ++k) v[k] = lds[lds_pad(k * T + tau) * LSTRIDE];
 #pragma unroll
-        for (int k = 1; k < R; ++k) v[k] = c_mulc(v[k], tw.w[0][k]);
+        for (int k = 1; k < R; ++k) v[k] = c_mulc(v[k], tw.get(0, k));
     }
     dft_reg<R, +1>(v);
 }

@@ -121,7 +121,15 @@ struct ConvGeo {
     int Do, Ho, Wo;               // output [N][Do][Ho][Wo][Co]
     int taps, K, Kp;              // taps = kd kh kw, K = taps Ci, Kp = K rounded up to 16
 };
+// forward tile of a workgroup: TY output rows x Wo columns of one (n, oz)
+// plane; its input footprint kd x FY x FX voxels with channel stride CiP
+struct FwdTile {
+    int TY, FY, FX, CiP, tiles_y;
+};
 namespace sg {
+constexpr size_t kMaxConvLds = 65536;  // dynamic LDS of one forward workgroup
+FwdTile fwd_tile(const ConvGeo& c);
+size_t fwd_lds_bytes(const ConvGeo& c);
 hipError_t conv_forward(const ConvGeo& c, const void* x, const void* w, const float* bias,
                         const int4* taps, int epi, void* ybf, float* yf, float* zkeep,
                         hipStream_t s);

@@ -116,6 +116,15 @@ hipError_t launch_plan(const Geom& g, const Plan& p, bool with_h, hipStream_t s)
 // ---------------------------------------------------------------------------
 // persistent forward march
 
+// LDS of one workgroup's row or column unit (the larger of the two)
+template <int NX, int NY>
+__host__ __device__ constexpr size_t march_data_lds() {
+    return sizeof(float2) * (units_per_block<NX>() * lds_size<NX>() >
+                                     units_per_block<NY>() * lds_size<NY>()
+                                 ? units_per_block<NX>() * lds_size<NX>()
+                                 : units_per_block<NY>() * lds_size<NY>());
+}
+
 // Up to kMaxFields marches of one geometry run in lockstep: every pass covers
 // the units of all fields, so the two grid barriers of a step are shared and a
 // workgroup's loads and stores of one unit overlap the work on the next.
@@ -132,8 +141,13 @@ struct MarchArgs {
     float k0dz;
 };
 
-template <int NX, int NY>
-__global__ __launch_bounds__(kBlock) void march_kernel(MarchArgs a) {
+// OCC = workgroups per CU.  OCC 1 keeps the twiddles in registers and walks
+// a workgroup's units two at a time (the second unit's loads in flight while
+// the first is transformed).  OCC 2 (several fields) reads the twiddles from
+// tables in LDS instead, so that two workgroups fit one CU (two waves per
+// SIMD) and one workgroup's memory waits overlap the other's arithmetic.
+template <int NX, int NY, int OCC>
+__global__ __launch_bounds__(kBlock, OCC) void march_kernel(MarchArgs a) {
     extern __shared__ float2 smem[];
     const int G = gridDim.x, v = virtual_block();
     const int rows_u = (a.ny + units_per_block<NX>() - 1) / units_per_block<NX>();
@@ -142,10 +156,23 @@ __global__ __launch_bounds__(kBlock) void march_kernel(MarchArgs a) {
     const size_t plane = (size_t)a.nx * a.ny;
     unsigned nbar = 0;
     bool abort = false;
-    Twiddles<NX, kR> twx;
-    Twiddles<NY, kR> twy;
-    twx.load(a.twx, threadIdx.x % (NX / kR));
-    twy.load(a.twy, threadIdx.x / units_per_block<NY>());
+    using TwX = typename std::conditional<OCC == 1, Twiddles<NX, kR>, LdsTwiddles<NX, kR>>::type;
+    using TwY = typename std::conditional<OCC == 1, Twiddles<NY, kR>, LdsTwiddles<NY, kR>>::type;
+    TwX twx;
+    TwY twy;
+    if constexpr (OCC == 1) {
+        twx.load(a.twx, threadIdx.x % (NX / kR));
+        twy.load(a.twy, threadIdx.x / units_per_block<NY>());
+    } else {
+        float2* tabx = smem + march_data_lds<NX, NY>() / sizeof(float2);
+        float2* taby = tabx + NX;
+        for (int i = threadIdx.x; i < NX; i += kBlock) tabx[i] = a.twx[i];
+        for (int i = threadIdx.x; i < NY; i += kBlock) taby[i] = a.twy[i];
+        __syncthreads();
+        twx = TwX{tabx, (int)threadIdx.x % (NX / kR)};
+        twy = TwY{taby, (int)threadIdx.x / units_per_block<NY>()};
+    }
+    constexpr int PAIR = OCC == 1 ? 2 : 1;  // units per loop trip
     float d[kR];
     for (int i = 0; i < kR; ++i) d[i] = 0.f;
     for (int u = v; u < all_r; u += G) {
@@ -157,23 +184,52 @@ __global__ __launch_bounds__(kBlock) void march_kernel(MarchArgs a) {
     const bool one_row_unit = all_r <= G;
     const int fv = (v < all_r ? v : 0) / rows_u;
     for (int j = 0; j < a.steps; ++j) {
-        if (one_row_unit) load_dn<NX>(d, (v < all_r ? v : 0) - fv * rows_u, a.ny, a.dn[fv] + j * plane);
+        if (one_row_unit)
+            load_dn<NX>(d, (v < all_r ? v : 0) - fv * rows_u, a.ny, a.dn[fv] + j * plane);
         grid_sync(a.counter, ++nbar, abort);
-        for (int u = v; u < all_c; u += G) {
-            const int f = u / cols_u;
-            col_unit<NY, false>(u - f * cols_u, a.nx, a.work[f], a.H, twy, smem, nullptr, nullptr,
-                                nullptr);
+        for (int u = v; u < all_c; u += PAIR * G) {
+            const int u2 = u + G;
+            const bool two = PAIR == 2 && u2 < all_c;
+            const int f1 = u / cols_u, f2 = two ? u2 / cols_u : 0;
+            float2 va[kR], ha[kR], vb[kR], hb[kR];
+            col_load<NY>(u - f1 * cols_u, a.nx, a.work[f1], a.H, va, ha);
+            if (two) col_load<NY>(u2 - f2 * cols_u, a.nx, a.work[f2], a.H, vb, hb);
+            col_body<NY, false>(u - f1 * cols_u, a.nx, a.work[f1], twy, smem, nullptr, nullptr,
+                                nullptr, va, ha);
+            if (two)
+                col_body<NY, false>(u2 - f2 * cols_u, a.nx, a.work[f2], twy, smem, nullptr,
+                                    nullptr, nullptr, vb, hb);
         }
         grid_sync(a.counter, ++nbar, abort);
-        for (int u = v; u < all_r; u += G) {
-            const int f = u / rows_u, ru = u - f * rows_u;
-            if (!one_row_unit) load_dn<NX>(d, ru, a.ny, a.dn[f] + j * plane);
-            RowArgs ra{a.work[f], a.work[f], a.inten[f] ? a.inten[f] + j * plane : nullptr,
-                       nullptr, nullptr, nullptr, nullptr, a.k0dz};
+        for (int u = v; u < all_r; u += PAIR * G) {
+            const int u2 = u + G;
+            const bool two = PAIR == 2 && u2 < all_r;
+            const int f1 = u / rows_u, r1 = u - f1 * rows_u;
+            const int f2 = two ? u2 / rows_u : 0, r2 = two ? u2 - f2 * rows_u : 0;
+            float2 va[kR], vb[kR];
+            float db[kR];
+            row_load<NX, kSpecIn>(r1, a.ny, a.work[f1], va);
+            if (!one_row_unit) load_dn<NX>(d, r1, a.ny, a.dn[f1] + j * plane);
+            if (two) {
+                row_load<NX, kSpecIn>(r2, a.ny, a.work[f2], vb);
+                load_dn<NX>(db, r2, a.ny, a.dn[f2] + j * plane);
+            }
+            const RowArgs ra{a.work[f1], a.work[f1],
+                             a.inten[f1] ? a.inten[f1] + j * plane : nullptr, nullptr, nullptr,
+                             nullptr, nullptr, a.k0dz};
             if (j + 1 < a.steps)
-                row_unit<NX, kSpecIn, kScreen, kSpecOut>(ru, a.ny, ra, d, twx, smem);
+                row_body<NX, kSpecIn, kScreen, kSpecOut>(r1, a.ny, ra, d, twx, smem, va);
             else
-                row_unit<NX, kSpecIn, kScreen, kNaturalOut>(ru, a.ny, ra, d, twx, smem);
+                row_body<NX, kSpecIn, kScreen, kNaturalOut>(r1, a.ny, ra, d, twx, smem, va);
+            if (two) {
+                const RowArgs rb{a.work[f2], a.work[f2],
+                                 a.inten[f2] ? a.inten[f2] + j * plane : nullptr, nullptr,
+                                 nullptr, nullptr, nullptr, a.k0dz};
+                if (j + 1 < a.steps)
+                    row_body<NX, kSpecIn, kScreen, kSpecOut>(r2, a.ny, rb, db, twx, smem, vb);
+                else
+                    row_body<NX, kSpecIn, kScreen, kNaturalOut>(r2, a.ny, rb, db, twx, smem, vb);
+            }
         }
     }
 }
@@ -423,10 +479,10 @@ static size_t persistent_lds() {
 }
 
 template <int NX, int NY>
-static int persistent_grid(int nx, int ny, int fields = 1) {
+static int persistent_grid(int nx, int ny, int fields = 1, int per_cu = 1) {
     const int rows_u = (ny + units_per_block<NX>() - 1) / units_per_block<NX>();
     const int cols_u = (nx + units_per_block<NY>() - 1) / units_per_block<NY>();
-    const int cus = device_cus();
+    const int cus = device_cus() * per_cu;
     const int grid = (rows_u > cols_u ? rows_u : cols_u) * fields;
     return grid > cus ? cus : grid;
 }
@@ -495,7 +551,14 @@ hipError_t launch_forward(const Geom& g, const Plan& p, const MarchIO* io, int f
     return dispatch2(g.nx, g.ny, [&](auto xc, auto yc) {
         constexpr int NX = decltype(xc)::value, NY = decltype(yc)::value;
         void* args[] = {&a};
-        return hipLaunchCooperativeKernel(reinterpret_cast<const void*>(&march_kernel<NX, NY>),
+        if constexpr (NX >= 512 && NY >= 512) {
+            if (fields >= 2)
+                return hipLaunchCooperativeKernel(
+                    reinterpret_cast<const void*>(&march_kernel<NX, NY, 2>),
+                    dim3(persistent_grid<NX, NY>(g.nx, g.ny, fields, 2)), dim3(kBlock), args,
+                    (unsigned)(march_data_lds<NX, NY>() + sizeof(float2) * (NX + NY)), s);
+        }
+        return hipLaunchCooperativeKernel(reinterpret_cast<const void*>(&march_kernel<NX, NY, 1>),
                                           dim3(persistent_grid<NX, NY>(g.nx, g.ny, fields)),
                                           dim3(kBlock), args, (unsigned)persistent_lds<NX, NY>(),
                                           s);

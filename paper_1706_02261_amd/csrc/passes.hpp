@@ -118,10 +118,27 @@ struct RowArgs {
     float k0dz;
 };
 
-template <int NX, int IN, int OPS, int OUT>
-__device__ __forceinline__ void row_unit(int unit, int ny, const RowArgs& a,
-                                         const float (&d)[kR], const Twiddles<NX, kR>& twx,
-                                         float2* smem) {
+// A row unit's field values (kSpecIn: spectrum, kNaturalIn: natural order);
+// split from the computation so that a workgroup can issue the loads of its
+// next unit before it works on the current one.
+template <int NX, int IN>
+__device__ __forceinline__ void row_load(int unit, int ny, const float2* src, float2 (&v)[kR]) {
+    constexpr int T = NX / kR, B = units_per_block<NX>();
+    const int row = unit * B + threadIdx.x / T, tau = threadIdx.x % T;
+    const size_t rowoff = (size_t)(row < ny ? row : 0) * NX;
+    if constexpr (IN == kZeroIn) {
+#pragma unroll
+        for (int i = 0; i < kR; ++i) v[i] = make_float2(0.f, 0.f);
+    } else {
+#pragma unroll
+        for (int i = 0; i < kR; ++i) v[i] = ld_shared_field(src + rowoff + i * T + tau);
+    }
+}
+
+template <int NX, int IN, int OPS, int OUT, typename Tw>
+__device__ __forceinline__ void row_body(int unit, int ny, const RowArgs& a,
+                                         const float (&d)[kR], const Tw& twx, float2* smem,
+                                         float2 (&v)[kR]) {
     constexpr int T = NX / kR, B = units_per_block<NX>();
     const int sub = threadIdx.x / T, tau = threadIdx.x % T;
     const int row = unit * B + sub;
@@ -129,18 +146,7 @@ __device__ __forceinline__ void row_unit(int unit, int ny, const RowArgs& a,
     const size_t rowoff = (size_t)(on ? row : 0) * NX;
     float2* lds = smem + sub * lds_size<NX>();
     const RowSync<NX> sync;
-    float2 v[kR];
-    if constexpr (IN == kZeroIn) {
-#pragma unroll
-        for (int i = 0; i < kR; ++i) v[i] = make_float2(0.f, 0.f);
-    } else if constexpr (IN == kNaturalIn) {
-#pragma unroll
-        for (int i = 0; i < kR; ++i) v[i] = ld_shared_field(a.src + rowoff + i * T + tau);
-    } else {
-#pragma unroll
-        for (int r = 0; r < kR; ++r) v[r] = ld_shared_field(a.src + rowoff + r * T + tau);
-        fft_inverse<NX, kR, 1>(v, lds, tau, twx, sync);
-    }
+    if constexpr (IN == kSpecIn) fft_inverse<NX, kR, 1>(v, lds, tau, twx, sync);
     if constexpr (OPS == kScreen) {
         float ph[kR];
 #pragma unroll
@@ -189,15 +195,36 @@ __device__ __forceinline__ void row_unit(int unit, int ny, const RowArgs& a,
     }
 }
 
+template <int NX, int IN, int OPS, int OUT, typename Tw>
+__device__ __forceinline__ void row_unit(int unit, int ny, const RowArgs& a,
+                                         const float (&d)[kR], const Tw& twx, float2* smem) {
+    float2 v[kR];
+    row_load<NX, IN>(unit, ny, a.src, v);
+    row_body<NX, IN, OPS, OUT>(unit, ny, a, d, twx, smem, v);
+}
+
 // Column pass on a working buffer: forward column FFTs, x H (or conj(H)),
 // inverse column FFTs.  With spec_out, the multiplied spectrum is also written
 // to spec_out in natural DFT order (the pupil-plane gradient).
-template <int NY, bool CONJ>
-__device__ __forceinline__ void col_unit(int unit, int nx, float2* work,
-                                         const float2* __restrict__ H,
-                                         const Twiddles<NY, kR>& twy, float2* smem,
+template <int NY>
+__device__ __forceinline__ void col_load(int unit, int nx, const float2* work,
+                                         const float2* __restrict__ H, float2 (&v)[kR],
+                                         float2 (&h)[kR]) {
+    constexpr int T = NY / kR, W = units_per_block<NY>();
+    const int c = unit * W + threadIdx.x % W, t = threadIdx.x / W;
+    const size_t col = c < nx ? (size_t)c : 0;
+#pragma unroll
+    for (int i = 0; i < kR; ++i) v[i] = ld_shared_field(work + (size_t)(i * T + t) * nx + col);
+#pragma unroll
+    for (int r = 0; r < kR; ++r) h[r] = H[(size_t)(r * T + t) * nx + col];
+}
+
+template <int NY, bool CONJ, typename Tw>
+__device__ __forceinline__ void col_body(int unit, int nx, float2* work, const Tw& twy,
+                                         float2* smem,
                                          float2* spec_out, const int* __restrict__ permx,
-                                         const int* __restrict__ permy) {
+                                         const int* __restrict__ permy, float2 (&v)[kR],
+                                         const float2 (&h)[kR]) {
     constexpr int T = NY / kR, W = units_per_block<NY>();
     const int w = threadIdx.x % W, t = threadIdx.x / W;
     const int c = unit * W + w;
@@ -205,11 +232,6 @@ __device__ __forceinline__ void col_unit(int unit, int nx, float2* work,
     const size_t col = on ? (size_t)c : 0;
     float2* lds = smem + w;
     const BlockSync sync;
-    float2 v[kR], h[kR];
-#pragma unroll
-    for (int i = 0; i < kR; ++i) v[i] = ld_shared_field(work + (size_t)(i * T + t) * nx + col);
-#pragma unroll
-    for (int r = 0; r < kR; ++r) h[r] = H[(size_t)(r * T + t) * nx + col];
     fft_forward<NY, kR, W>(v, lds, t, twy, sync);
 #pragma unroll
     for (int r = 0; r < kR; ++r) v[r] = CONJ ? c_mulc(v[r], h[r]) : c_mul(v[r], h[r]);
@@ -223,6 +245,17 @@ __device__ __forceinline__ void col_unit(int unit, int nx, float2* work,
 #pragma unroll
         for (int i = 0; i < kR; ++i) st_shared_field(work + (size_t)(i * T + t) * nx + col, v[i]);
     }
+}
+
+template <int NY, bool CONJ, typename Tw>
+__device__ __forceinline__ void col_unit(int unit, int nx, float2* work,
+                                         const float2* __restrict__ H, const Tw& twy,
+                                         float2* smem,
+                                         float2* spec_out, const int* __restrict__ permx,
+                                         const int* __restrict__ permy) {
+    float2 v[kR], h[kR];
+    col_load<NY>(unit, nx, work, H, v, h);
+    col_body<NY, CONJ>(unit, nx, work, twy, smem, spec_out, permx, permy, v, h);
 }
 
 // ---------------------------------------------------------------------------

@@ -41,27 +41,54 @@ __device__ __forceinline__ float sigmoid(float z) { return 1.f / (1.f + expf(-z)
 //   EPI 0: ReLU, bf16 channels-last output
 //   EPI 1: softplus, fp32 output [N][Co][Ho][Wo] (Do == 1) and the
 //          pre-activation kept in the same layout
-// One wave computes 32 output channels x 32 output positions.
+//
+// A workgroup computes 32 output channels of an output tile of TY rows x Wo
+// columns of one (n, oz) plane (TY = min(Ho, 128 / Wo)); wave w takes the
+// flattened tile positions [32 w, 32 w + 32).  The tile's input footprint,
+// kd x FY x FX voxels with FY = (TY - 1) sh + kh and FX = (Wo - 1) sw + kw, is
+// staged in LDS once (zero outside the input; channel stride CiP = Ci, plus 8
+// when Ci >= 32 against bank conflicts), so each input voxel crosses the
+// memory system once per tile instead of once per tap.
 
 template <int EPI>
 __global__ __launch_bounds__(256) void conv_fwd_kernel(const u16* __restrict__ x,
                                                        const u16* __restrict__ w,
                                                        const float* __restrict__ bias, ConvGeo c,
-                                                       const int4* __restrict__ taps, u16* ybf,
-                                                       float* yf, float* zkeep) {
+                                                       FwdTile t, const int4* __restrict__ taps,
+                                                       u16* ybf, float* yf, float* zkeep) {
+    extern __shared__ uint4 lds_raw[];
+    u16* xs = reinterpret_cast<u16*>(lds_raw);
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6, half = lane >> 5;
-    const long P = (long)c.N * c.Do * c.Ho * c.Wo;
-    const long p = ((long)blockIdx.x * 4 + wave) * 32 + (lane & 31);
-    const bool pon = p < P;
-    long q = pon ? p : 0;
-    const int ox = (int)(q % c.Wo);
-    q /= c.Wo;
-    const int oy = (int)(q % c.Ho);
-    q /= c.Ho;
-    const int oz = (int)(q % c.Do);
-    const int n = (int)(q / c.Do);
-    const int iz0 = oz * c.sd - c.pd, iy0 = oy * c.sh - c.ph, ix0 = ox * c.sw - c.pw;
+    int b = blockIdx.x;
+    const int ty = b % t.tiles_y;
+    b /= t.tiles_y;
+    const int oz = b % c.Do, n = b / c.Do;
+    const int oy0 = ty * t.TY;
+    const int iz0 = oz * c.sd - c.pd, iy0 = oy0 * c.sh - c.ph, ix0 = -c.pw;
+    const int cch = c.Ci / 8;
+    const int total = c.kd * t.FY * t.FX * cch;
     const u16* xn = x + (size_t)n * c.D * c.H * c.W * c.Ci;
+    for (int e = threadIdx.x; e < total; e += 256) {
+        int q = e;
+        const int c8 = q % cch;
+        q /= cch;
+        const int fx = q % t.FX;
+        q /= t.FX;
+        const int fy = q % t.FY, fz = q / t.FY;
+        const int iz = iz0 + fz, iy = iy0 + fy, ix = ix0 + fx;
+        uint4 v = make_uint4(0, 0, 0, 0);
+        if ((unsigned)iz < (unsigned)c.D && (unsigned)iy < (unsigned)c.H &&
+            (unsigned)ix < (unsigned)c.W)
+            v = *reinterpret_cast<const uint4*>(xn + (((size_t)iz * c.H + iy) * c.W + ix) * c.Ci +
+                                                c8 * 8);
+        *reinterpret_cast<uint4*>(xs + ((fz * t.FY + fy) * t.FX + fx) * t.CiP + c8 * 8) = v;
+    }
+    __syncthreads();
+    const int pl = wave * 32 + (lane & 31);
+    const int oyl = pl / c.Wo, ox = pl % c.Wo;
+    const int oy = oy0 + oyl;
+    const bool pon = oyl < t.TY && oy < c.Ho;
+    const int base = pon ? (oyl * c.sh * t.FX + ox * c.sw) * t.CiP : 0;
     const int co0 = blockIdx.y * 32;
     const u16* wrow = w + (size_t)(co0 + (lane & 31)) * c.Kp;
     f32x16 acc = {};
@@ -70,16 +97,14 @@ __global__ __launch_bounds__(256) void conv_fwd_kernel(const u16* __restrict__ x
         const uint4 av = *reinterpret_cast<const uint4*>(wrow + kk);
         uint4 bv = make_uint4(0, 0, 0, 0);
         if (kk < c.K && pon) {
-            const int4 t = taps[kk / 8];  // (a, b, cc, ci) of this 8-channel chunk
-            const int iz = iz0 + t.x, iy = iy0 + t.y, ix = ix0 + t.z;
-            if ((unsigned)iz < (unsigned)c.D && (unsigned)iy < (unsigned)c.H &&
-                (unsigned)ix < (unsigned)c.W)
-                bv = *reinterpret_cast<const uint4*>(
-                    xn + (((size_t)iz * c.H + iy) * c.W + ix) * c.Ci + t.w);
+            const int4 tp = taps[kk / 8];  // (a, b, cc, ci) of this 8-channel chunk
+            bv = *reinterpret_cast<const uint4*>(
+                xs + base + ((tp.x * t.FY + tp.y) * t.FX + tp.z) * t.CiP + tp.w);
         }
         acc = mfma(av, bv, acc);
     }
     if (!pon) return;
+    const size_t p = (((size_t)n * c.Do + oz) * c.Ho + oy) * c.Wo + ox;
 #pragma unroll
     for (int g = 0; g < 4; ++g) {
         const int cob = co0 + 8 * g + 4 * half;
@@ -87,7 +112,7 @@ __global__ __launch_bounds__(256) void conv_fwd_kernel(const u16* __restrict__ x
             u16 o[4];
 #pragma unroll
             for (int i = 0; i < 4; ++i) o[i] = f2bf(fmaxf(acc[4 * g + i] + bias[cob + i], 0.f));
-            *reinterpret_cast<uint2*>(ybf + (size_t)p * c.Co + cob) =
+            *reinterpret_cast<uint2*>(ybf + p * c.Co + cob) =
                 make_uint2(o[0] | ((unsigned)o[1] << 16), o[2] | ((unsigned)o[3] << 16));
         } else {
 #pragma unroll
@@ -480,17 +505,34 @@ static unsigned grid_for(long n, int per = 256) {
     return (unsigned)(b < 65535 ? (b > 0 ? b : 1) : 65535);
 }
 
+FwdTile fwd_tile(const ConvGeo& c) {
+    FwdTile t{};
+    const int rows = 128 / c.Wo > 0 ? 128 / c.Wo : 1;
+    t.TY = c.Ho < rows ? c.Ho : rows;
+    t.FY = (t.TY - 1) * c.sh + c.kh;
+    t.FX = (c.Wo - 1) * c.sw + c.kw;
+    t.CiP = c.Ci + (c.Ci >= 32 ? 8 : 0);
+    t.tiles_y = (c.Ho + t.TY - 1) / t.TY;
+    return t;
+}
+
+size_t fwd_lds_bytes(const ConvGeo& c) {
+    const FwdTile t = fwd_tile(c);
+    return sizeof(u16) * (size_t)c.kd * t.FY * t.FX * t.CiP;
+}
+
 hipError_t conv_forward(const ConvGeo& c, const void* x, const void* w, const float* bias,
                         const int4* taps, int epi, void* ybf, float* yf, float* zkeep,
                         hipStream_t s) {
-    const long P = (long)c.N * c.Do * c.Ho * c.Wo;
-    dim3 grid((unsigned)((P + 127) / 128), c.Co / 32);
+    const FwdTile t = fwd_tile(c);
+    const size_t lds = fwd_lds_bytes(c);
+    dim3 grid((unsigned)((long)c.N * c.Do * t.tiles_y), c.Co / 32);
     if (epi == 0)
-        conv_fwd_kernel<0><<<grid, 256, 0, s>>>((const u16*)x, (const u16*)w, bias, c, taps,
-                                                (u16*)ybf, yf, zkeep);
+        conv_fwd_kernel<0><<<grid, 256, lds, s>>>((const u16*)x, (const u16*)w, bias, c, t, taps,
+                                                  (u16*)ybf, yf, zkeep);
     else
-        conv_fwd_kernel<1><<<grid, 256, 0, s>>>((const u16*)x, (const u16*)w, bias, c, taps,
-                                                (u16*)ybf, yf, zkeep);
+        conv_fwd_kernel<1><<<grid, 256, lds, s>>>((const u16*)x, (const u16*)w, bias, c, t, taps,
+                                                  (u16*)ybf, yf, zkeep);
     return hipGetLastError();
 }
 

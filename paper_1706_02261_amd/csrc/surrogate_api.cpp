@@ -287,6 +287,11 @@ int check_conv_geo(const int* geom, ConvGeo* c, bool data_grad) {
     const double P = (double)c->N * c->Do * c->Ho * c->Wo;
     if (in > 2e9 || out > 2e9 || P > 65535.0 * 2048.0 || c->K > (1 << 24))
         return fail(BPM_ERR_UNSUPPORTED_SIZE, "convolution too large");
+    if (c->Wo > 128 || sg::fwd_lds_bytes(*c) > sg::kMaxConvLds ||
+        (double)c->N * c->Do * sg::fwd_tile(*c).tiles_y > 2e9)
+        return fail(BPM_ERR_UNSUPPORTED_SIZE,
+                    "Wo=%d: output rows of at most 128 and an input tile of at most %zu bytes",
+                    c->Wo, sg::kMaxConvLds);
     return BPM_OK;
 }
 
