@@ -236,6 +236,7 @@ struct Twiddles {
         }
     }
     __device__ __forceinline__ float2 get(int s, int m) const { return w[s][m]; }
+    static constexpr bool kOpaqueIndex = false;
 };
 
 // The same twiddles read on use from a table tw[e] = exp(-2 pi i e / N) in LDS
@@ -243,6 +244,10 @@ struct Twiddles {
 // across the passes, one LDS read per twiddle.
 template <int N, int R>
 struct LdsTwiddles {
+    // used where registers are short: the transforms then hide the thread
+    // index from the compiler, so that it recomputes their LDS addresses on
+    // every call instead of keeping them all live across the caller's loop
+    static constexpr bool kOpaqueIndex = true;
     const float2* tab;
     int tau;
     __device__ __forceinline__ float2 get(int s, int m) const {
@@ -268,6 +273,7 @@ __device__ __forceinline__ void fft_forward(float2 (&v)[R], float2* lds, int tau
                                             Sync sync) {
     using L = FftLayout<N, R>;
     constexpr int T = L::T;
+    if constexpr (Tw::kOpaqueIndex) asm volatile("" : "+v"(tau));
     dft_reg<R, -1>(v);
     if constexpr (L::S > 1) {
 #pragma unroll
@@ -305,6 +311,7 @@ __device__ __forceinline__ void fft_inverse(float2 (&v)[R], float2* lds, int tau
                                             Sync sync) {
     using L = FftLayout<N, R>;
     constexpr int T = L::T;
+    if constexpr (Tw::kOpaqueIndex) asm volatile("" : "+v"(tau));
     if constexpr (L::S > 1) {
         static_for<1, L::S>([&](auto ic) {
             constexpr int s = L::S - decltype(ic)::value;  // S-1 down to 1
