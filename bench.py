@@ -269,6 +269,8 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--slices", type=int, default=1024, help="march depth (default 1024)")
     ap.add_argument("--no-psf", action="store_true", help="skip the surrogate vs BPM PSF rates")
+    ap.add_argument("--psf-only", action="store_true",
+                    help="only the surrogate vs BPM PSF rates (for profiling those kernels)")
     ap.add_argument("--no-extra", action="store_true",
                     help="skip the adjoint and uneven-batch rates")
     ap.add_argument("--copy-mib", type=int, default=0,
@@ -289,6 +291,9 @@ def main():
     import synth
 
     dev = torch.device("cuda:0")
+    if args.psf_only:
+        print(json.dumps({"metric": "surrogate vs BPM PSFs/s", "psf": psf_rates(dev)}), flush=True)
+        return
     t_gen = time.perf_counter()
     g, u0, dn_host = synth.config2_detection(steps=args.slices)
     gl, u0_ls, dn_ls = synth.config2_light_sheet(g, dn_host)

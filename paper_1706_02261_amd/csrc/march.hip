@@ -175,37 +175,40 @@ __global__ __launch_bounds__(kBlock, OCC) void march_kernel(MarchArgs a) {
     constexpr int PAIR = OCC == 1 ? 2 : 1;  // units per loop trip
     float d[kR];
     for (int i = 0; i < kR; ++i) d[i] = 0.f;
+    // combined unit u is unit u / fields of field u % fields: the fields'
+    // units of one column range sit next to each other, so the workgroups of
+    // an XCD share that range's slice of the propagator table in its L2
+    const int F = a.fields;
     for (int u = v; u < all_r; u += G) {
-        const int f = u / rows_u;
+        const int f = u % F;
         RowArgs ra{a.field_in[f], a.work[f], nullptr, nullptr, nullptr, nullptr, nullptr, a.k0dz};
-        row_unit<NX, kNaturalIn, kNoOps, kSpecOut>(u - f * rows_u, a.ny, ra, d, twx, smem);
+        row_unit<NX, kNaturalIn, kNoOps, kSpecOut>(u / F, a.ny, ra, d, twx, smem);
     }
     // a workgroup with a single row unit fetches its dn slice during the column pass
     const bool one_row_unit = all_r <= G;
-    const int fv = (v < all_r ? v : 0) / rows_u;
+    const int vv = v < all_r ? v : 0;
     for (int j = 0; j < a.steps; ++j) {
-        if (one_row_unit)
-            load_dn<NX>(d, (v < all_r ? v : 0) - fv * rows_u, a.ny, a.dn[fv] + j * plane);
+        if (one_row_unit) load_dn<NX>(d, vv / F, a.ny, a.dn[vv % F] + j * plane);
         grid_sync(a.counter, ++nbar, abort);
         for (int u = v; u < all_c; u += PAIR * G) {
             const int u2 = u + G;
             const bool two = PAIR == 2 && u2 < all_c;
-            const int f1 = u / cols_u, f2 = two ? u2 / cols_u : 0;
+            const int f1 = u % F, f2 = u2 % F;
             float2 va[kR], ha[kR], vb[kR], hb[kR];
-            col_load<NY>(u - f1 * cols_u, a.nx, a.work[f1], a.H, va, ha);
-            if (two) col_load<NY>(u2 - f2 * cols_u, a.nx, a.work[f2], a.H, vb, hb);
-            col_body<NY, false>(u - f1 * cols_u, a.nx, a.work[f1], twy, smem, nullptr, nullptr,
-                                nullptr, va, ha);
+            col_load<NY>(u / F, a.nx, a.work[f1], a.H, va, ha);
+            if (two) col_load<NY>(u2 / F, a.nx, a.work[f2], a.H, vb, hb);
+            col_body<NY, false>(u / F, a.nx, a.work[f1], twy, smem, nullptr, nullptr, nullptr, va,
+                                ha);
             if (two)
-                col_body<NY, false>(u2 - f2 * cols_u, a.nx, a.work[f2], twy, smem, nullptr,
-                                    nullptr, nullptr, vb, hb);
+                col_body<NY, false>(u2 / F, a.nx, a.work[f2], twy, smem, nullptr, nullptr,
+                                    nullptr, vb, hb);
         }
         grid_sync(a.counter, ++nbar, abort);
         for (int u = v; u < all_r; u += PAIR * G) {
             const int u2 = u + G;
             const bool two = PAIR == 2 && u2 < all_r;
-            const int f1 = u / rows_u, r1 = u - f1 * rows_u;
-            const int f2 = two ? u2 / rows_u : 0, r2 = two ? u2 - f2 * rows_u : 0;
+            const int f1 = u % F, r1 = u / F;
+            const int f2 = u2 % F, r2 = two ? u2 / F : 0;
             float2 va[kR], vb[kR];
             float db[kR];
             row_load<NX, kSpecIn>(r1, a.ny, a.work[f1], va);
