@@ -230,7 +230,7 @@ int bpm_point_sources(const int* positions, const float* phases, int n_src, int 
  *   psf_out        [batch][32][32][32] float32 PSF intensity (plane, y, x).
  *   pred_err       [batch] float32 predicted relative L2 error of each PSF.
  *   workspace      psf_surrogate_workspace_size(batch, 0) bytes, 256-byte
- *                  aligned; batches are processed in chunks of 256 samples.
+ *                  aligned; batches are processed in chunks of 1024 samples.
  * BF16 operands, FP32 accumulation on the matrix cores.  batch = 0 is a no-op. */
 int psf_surrogate_infer(const void* weights_bf16, size_t weights_bytes,
                         const float* dn_patches, const float* depth, int batch,

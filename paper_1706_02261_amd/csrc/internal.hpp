@@ -130,9 +130,13 @@ namespace sg {
 constexpr size_t kMaxConvLds = 65536;  // dynamic LDS of one forward workgroup
 FwdTile fwd_tile(const ConvGeo& c);
 size_t fwd_lds_bytes(const ConvGeo& c);
+// in_mode 0: x is bf16 channels-last; 1 (with epi 0): x is the fp32 dn patch
+// [N][64][32][32] and the input channels are formed while staging (depth[N]);
+// 2 (with epi 1): x is the bf16 map at half the height and width, read
+// through a nearest x2 upsampling
 hipError_t conv_forward(const ConvGeo& c, const void* x, const void* w, const float* bias,
                         const int4* taps, int epi, void* ybf, float* yf, float* zkeep,
-                        hipStream_t s);
+                        hipStream_t s, int in_mode = 0, const float* depth = nullptr);
 hipError_t conv_backward_data(const ConvGeo& c, const void* dy, const void* wt,
                               const void* xact, const int4* taps_t, void* dx, hipStream_t s);
 hipError_t conv_backward_weight(const ConvGeo& c, const void* x, const void* dy,

@@ -50,8 +50,28 @@ __device__ __forceinline__ float sigmoid(float z) { return 1.f / (1.f + expf(-z)
 // when Ci >= 32 against bank conflicts), so each input voxel crosses the
 // memory system once per tile instead of once per tap.
 
-template <int EPI>
-__global__ __launch_bounds__(256) void conv_fwd_kernel(const u16* __restrict__ x,
+// The network's input channels of voxel (z, y, x) of a [64][32][32] patch:
+// dn / 0.05, the mask [z >= depth], (y - 15.5) / 16, (x - 15.5) / 16, their
+// squared norm, zeros.
+__device__ __forceinline__ uint4 input_channels(float dn, float depth, int z, int y, int x) {
+    const float m = (float)z >= depth ? 1.f : 0.f;
+    const float cy = ((float)y - 15.5f) * 0.0625f, cx = ((float)x - 15.5f) * 0.0625f;
+    const float r2 = cy * cy + cx * cx;
+    return make_uint4(f2bf(dn * 20.f) | ((unsigned)f2bf(m) << 16),
+                      f2bf(cy) | ((unsigned)f2bf(cx) << 16), f2bf(r2), 0);
+}
+
+// Where the staged input comes from:
+//   kInBf16   x is the bf16 activation [N][D][H][W][Ci];
+//   kInPatch  x is the fp32 dn patch [N][64][32][32] (Ci = 8): the network's
+//             input channels are formed while staging (depth[] per sample);
+//   kInUp2    x is the bf16 map [N][D][H/2][W/2][Ci] read through a nearest
+//             x2 upsampling in y and x.
+enum ConvIn : int { kInBf16 = 0, kInPatch = 1, kInUp2 = 2 };
+
+template <int EPI, int IN>
+__global__ __launch_bounds__(256) void conv_fwd_kernel(const void* __restrict__ xin,
+                                                       const float* __restrict__ depth,
                                                        const u16* __restrict__ w,
                                                        const float* __restrict__ bias, ConvGeo c,
                                                        FwdTile t, const int4* __restrict__ taps,
@@ -67,7 +87,6 @@ __global__ __launch_bounds__(256) void conv_fwd_kernel(const u16* __restrict__ x
     const int iz0 = oz * c.sd - c.pd, iy0 = oy0 * c.sh - c.ph, ix0 = -c.pw;
     const int cch = c.Ci / 8;
     const int total = c.kd * t.FY * t.FX * cch;
-    const u16* xn = x + (size_t)n * c.D * c.H * c.W * c.Ci;
     for (int e = threadIdx.x; e < total; e += 256) {
         int q = e;
         const int c8 = q % cch;
@@ -78,9 +97,21 @@ __global__ __launch_bounds__(256) void conv_fwd_kernel(const u16* __restrict__ x
         const int iz = iz0 + fz, iy = iy0 + fy, ix = ix0 + fx;
         uint4 v = make_uint4(0, 0, 0, 0);
         if ((unsigned)iz < (unsigned)c.D && (unsigned)iy < (unsigned)c.H &&
-            (unsigned)ix < (unsigned)c.W)
-            v = *reinterpret_cast<const uint4*>(xn + (((size_t)iz * c.H + iy) * c.W + ix) * c.Ci +
-                                                c8 * 8);
+            (unsigned)ix < (unsigned)c.W) {
+            if constexpr (IN == kInBf16) {
+                const u16* xn = static_cast<const u16*>(xin) + (size_t)n * c.D * c.H * c.W * c.Ci;
+                v = *reinterpret_cast<const uint4*>(
+                    xn + (((size_t)iz * c.H + iy) * c.W + ix) * c.Ci + c8 * 8);
+            } else if constexpr (IN == kInPatch) {
+                const float* dn = static_cast<const float*>(xin) + (size_t)n * c.D * c.H * c.W;
+                v = input_channels(dn[((size_t)iz * c.H + iy) * c.W + ix], depth[n], iz, iy, ix);
+            } else {
+                const int h2 = c.H / 2, w2 = c.W / 2;
+                const u16* xn = static_cast<const u16*>(xin) + (size_t)n * c.D * h2 * w2 * c.Ci;
+                v = *reinterpret_cast<const uint4*>(
+                    xn + (((size_t)iz * h2 + iy / 2) * w2 + ix / 2) * c.Ci + c8 * 8);
+            }
+        }
         *reinterpret_cast<uint4*>(xs + ((fz * t.FY + fy) * t.FX + fx) * t.CiP + c8 * 8) = v;
     }
     __syncthreads();
@@ -303,12 +334,7 @@ __global__ void prep_input_kernel(const float* __restrict__ dn, const float* __r
          e += (long)gridDim.x * blockDim.x) {
         const long n = e / (64 * 32 * 32);
         const int z = (int)(e / (32 * 32) % 64), y = (int)(e / 32 % 32), x = (int)(e % 32);
-        const float m = (float)z >= depth[n] ? 1.f : 0.f;
-        const float cy = ((float)y - 15.5f) * 0.0625f, cx = ((float)x - 15.5f) * 0.0625f;
-        const float r2 = cy * cy + cx * cx;
-        uint4 v = make_uint4(f2bf(dn[e] * 20.f) | ((unsigned)f2bf(m) << 16),
-                             f2bf(cy) | ((unsigned)f2bf(cx) << 16), f2bf(r2), 0);
-        *reinterpret_cast<uint4*>(x0 + e * 8) = v;
+        *reinterpret_cast<uint4*>(x0 + e * 8) = input_channels(dn[e], depth[n], z, y, x);
     }
 }
 
@@ -370,16 +396,24 @@ __global__ void head_fwd_kernel(const u16* __restrict__ a, int hw, int C,
                                 const float* __restrict__ we, const float* __restrict__ be,
                                 float* __restrict__ pooled, float* __restrict__ epre,
                                 float* __restrict__ err) {
+    // blockDim.x = 256, C divides 256: 256 / C groups of C threads sum
+    // interleaved positions (consecutive threads read consecutive channels)
     __shared__ float part[256];
-    const int n = blockIdx.x;
+    const int n = blockIdx.x, ch = threadIdx.x % C, grp = threadIdx.x / C;
+    const int groups = blockDim.x / C;
+    float s = 0.f;
+    for (int i = grp; i < hw; i += groups) s += bf2f(a[((size_t)n * hw + i) * C + ch]);
+    part[threadIdx.x] = s;
+    __syncthreads();
     float dot = 0.f;
-    for (int ch = threadIdx.x; ch < C; ch += blockDim.x) {
-        float s = 0.f;
-        for (int i = 0; i < hw; ++i) s += bf2f(a[((size_t)n * hw + i) * C + ch]);
-        s /= (float)hw;
-        pooled[(size_t)n * C + ch] = s;
-        dot += we[ch] * s;
+    if (threadIdx.x < C) {
+        float t = 0.f;
+        for (int g = 0; g < groups; ++g) t += part[g * C + ch];
+        t /= (float)hw;
+        pooled[(size_t)n * C + ch] = t;
+        dot = we[ch] * t;
     }
+    __syncthreads();
     part[threadIdx.x] = dot;
     __syncthreads();
     for (int st = blockDim.x / 2; st > 0; st >>= 1) {
@@ -523,16 +557,25 @@ size_t fwd_lds_bytes(const ConvGeo& c) {
 
 hipError_t conv_forward(const ConvGeo& c, const void* x, const void* w, const float* bias,
                         const int4* taps, int epi, void* ybf, float* yf, float* zkeep,
-                        hipStream_t s) {
+                        hipStream_t s, int in_mode, const float* depth) {
     const FwdTile t = fwd_tile(c);
     const size_t lds = fwd_lds_bytes(c);
     dim3 grid((unsigned)((long)c.N * c.Do * t.tiles_y), c.Co / 32);
-    if (epi == 0)
-        conv_fwd_kernel<0><<<grid, 256, lds, s>>>((const u16*)x, (const u16*)w, bias, c, t, taps,
-                                                  (u16*)ybf, yf, zkeep);
+    const u16* wb = (const u16*)w;
+    if (in_mode == kInPatch && epi == 0)
+        conv_fwd_kernel<0, kInPatch><<<grid, 256, lds, s>>>(x, depth, wb, bias, c, t, taps,
+                                                            (u16*)ybf, yf, zkeep);
+    else if (in_mode == kInUp2 && epi == 1)
+        conv_fwd_kernel<1, kInUp2><<<grid, 256, lds, s>>>(x, depth, wb, bias, c, t, taps,
+                                                          (u16*)ybf, yf, zkeep);
+    else if (in_mode != kInBf16)
+        return hipErrorInvalidValue;
+    else if (epi == 0)
+        conv_fwd_kernel<0, kInBf16><<<grid, 256, lds, s>>>(x, depth, wb, bias, c, t, taps,
+                                                           (u16*)ybf, yf, zkeep);
     else
-        conv_fwd_kernel<1><<<grid, 256, lds, s>>>((const u16*)x, (const u16*)w, bias, c, t, taps,
-                                                  (u16*)ybf, yf, zkeep);
+        conv_fwd_kernel<1, kInBf16><<<grid, 256, lds, s>>>(x, depth, wb, bias, c, t, taps,
+                                                           (u16*)ybf, yf, zkeep);
     return hipGetLastError();
 }
 

@@ -25,7 +25,7 @@ using namespace bpm::abi;
 constexpr int kLayers = 6;
 constexpr int kPatchD = 64, kPatchHW = 32, kPlanes = 32, kInCh = 8;
 constexpr int kHeadC = 64;             // channels of the map the error head pools
-constexpr int kInferChunk = 256;       // samples per inference pass
+constexpr int kInferChunk = 1024;      // samples per inference pass
 constexpr int kMaxTrainBatch = 1024;
 
 struct LayerSpec {
@@ -186,10 +186,10 @@ WsLayout ws_layout(int B, bool training) {
         o += align_up(bytes);
         return at;
     };
-    for (int l = 0; l < kLayers - 1; ++l) w.act[l] = take(2 * in_elems(l) * B);
-    w.act[kLayers - 1] = 0;
+    // inference forms the input channels and the upsampled map while staging
+    for (int l = training ? 0 : 1; l < kLayers - 1; ++l) w.act[l] = take(2 * in_elems(l) * B);
     w.a5 = take(2 * out_elems(4) * B);
-    w.up = take(2 * in_elems(5) * B);
+    if (training) w.up = take(2 * in_elems(5) * B);
     w.pooled = take(sizeof(float) * kHeadC * B);
     w.epre = take(sizeof(float) * B);
     if (training) {
@@ -242,22 +242,31 @@ hipError_t tables_all(void* base, const PackLayout& k, bool transposed, hipStrea
 // (packed layout k) and `bias` (fp32 biases then head, param-layout order from
 // bias_begin).  The PSF goes to psf (fp32 [B][planes][32][32]), its
 // pre-activation to z (may be null), the predicted error to err.
+// With `training`, the stored input x0 and the upsampled map (which the
+// weight gradients read) are materialised; inference forms both on the fly
+// while staging the first and the last convolution's input tiles.  Either
+// way the convolutions see the same bf16 values.
 hipError_t forward(const void* wbase, const PackLayout& k, const float* bias, const float* dn,
                    const float* depth, int B, void* ws, const WsLayout& w, float* psf, float* z,
-                   float* err, hipStream_t s) {
+                   float* err, hipStream_t s, bool training) {
     const ParamLayout p = param_layout();
     auto bias_of = [&](int l) { return bias + (p.b[l] - p.bias_begin); };
-    hipError_t e = sg::prep_input(dn, depth, B, at<void>(ws, w.act[0]), s);
+    hipError_t e = hipSuccess;
+    if (training) e = sg::prep_input(dn, depth, B, at<void>(ws, w.act[0]), s);
     for (int l = 0; l < 5 && e == hipSuccess; ++l) {
         void* out = l < 4 ? at<void>(ws, w.act[l + 1]) : at<void>(ws, w.a5);
-        e = sg::conv_forward(layer_geo(l, B), at<void>(ws, w.act[l]), at<void>(wbase, k.wb[l]),
-                             bias_of(l), at<int4>(wbase, k.taps[l]), 0, out, nullptr, nullptr,
-                             s);
+        const bool patch = l == 0 && !training;
+        e = sg::conv_forward(layer_geo(l, B), patch ? (const void*)dn : at<void>(ws, w.act[l]),
+                             at<void>(wbase, k.wb[l]), bias_of(l), at<int4>(wbase, k.taps[l]), 0,
+                             out, nullptr, nullptr, s, patch ? 1 : 0, depth);
     }
-    if (e == hipSuccess) e = sg::upsample(at<void>(ws, w.a5), B, 16, 16, kHeadC, at<void>(ws, w.up), s);
+    if (e == hipSuccess && training)
+        e = sg::upsample(at<void>(ws, w.a5), B, 16, 16, kHeadC, at<void>(ws, w.up), s);
     if (e == hipSuccess)
-        e = sg::conv_forward(layer_geo(5, B), at<void>(ws, w.up), at<void>(wbase, k.wb[5]),
-                             bias_of(5), at<int4>(wbase, k.taps[5]), 1, nullptr, psf, z, s);
+        e = sg::conv_forward(layer_geo(5, B),
+                             training ? at<void>(ws, w.up) : at<void>(ws, w.a5),
+                             at<void>(wbase, k.wb[5]), bias_of(5), at<int4>(wbase, k.taps[5]), 1,
+                             nullptr, psf, z, s, training ? 0 : 2, depth);
     if (e == hipSuccess)
         e = sg::head_forward(at<void>(ws, w.a5), B, 16 * 16, kHeadC, bias + (p.we - p.bias_begin),
                              bias + (p.be - p.bias_begin), at<float>(ws, w.pooled),
@@ -389,7 +398,8 @@ int psf_surrogate_train_step(void* state, const float* dn, const float* depth,
     void* ws = workspace;
 
     hipError_t e = forward(state, L.pack, params + p.bias_begin, dn, depth, B, ws, w,
-                           at<float>(ws, w.psf), at<float>(ws, w.z), at<float>(ws, w.err), s);
+                           at<float>(ws, w.psf), at<float>(ws, w.z), at<float>(ws, w.err), s,
+                           true);
     if (e == hipSuccess) e = sg::fill_zero(grads, (long)p.total, s);
     if (e == hipSuccess) e = sg::fill_zero(loss_out, 2, s);
     if (e == hipSuccess)
@@ -498,7 +508,8 @@ int psf_surrogate_infer(const void* weights_bf16, size_t weights_bytes, const fl
     for (int n0 = 0; n0 < batch && e == hipSuccess; n0 += chunk) {
         const int B = batch - n0 < chunk ? batch - n0 : chunk;
         e = forward(weights_bf16, b.pack, at<float>(weights_bf16, b.bias), dn_patches + n0 * per_dn,
-                    depth + n0, B, workspace, w, psf_out + n0 * per_psf, nullptr, pred_err + n0, s);
+                    depth + n0, B, workspace, w, psf_out + n0 * per_psf, nullptr, pred_err + n0, s,
+                    false);
     }
     return device_status(e, "surrogate inference");
 }

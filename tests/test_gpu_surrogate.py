@@ -190,14 +190,14 @@ def test_inference_matches_oracle_and_is_batch_invariant():
     params[S.param_slices()["we"]] *= 50.0
     model = S.PSFSurrogate("cuda", params)
     blob = model.export()
-    dn, depth, _ = batch(300, 6)
+    dn, depth, _ = batch(1100, 6)
     dn_t, depth_t = torch.from_numpy(dn).cuda(), torch.from_numpy(depth).cuda()
-    psf, err = S.infer(blob, dn_t, depth_t)          # two chunks: 256 + 44
-    psf_a, err_a = S.infer(blob, dn_t[290:].contiguous(), depth_t[290:].contiguous())
+    psf, err = S.infer(blob, dn_t, depth_t)          # two chunks: 1024 + 76
+    psf_a, err_a = S.infer(blob, dn_t[1090:].contiguous(), depth_t[1090:].contiguous())
     torch.cuda.synchronize()
-    assert torch.equal(psf[290:], psf_a) and torch.equal(err[290:], err_a)
+    assert torch.equal(psf[1090:], psf_a) and torch.equal(err[1090:], err_a)
     p = oracle_params(params)
-    pick = [0, 255, 256, 299]
+    pick = [0, 1023, 1024, 1099]
     cache = net.forward(p, dn[pick], depth[pick], rnd=True)
     assert rel(psf[pick].double().cpu().numpy(), cache["psf"]) <= 5e-3
     assert rel(err[pick].double().cpu().numpy(), cache["err"]) <= 5e-3
