@@ -114,26 +114,51 @@ __global__ __launch_bounds__(256) void conv_fwd_kernel(const void* __restrict__ 
         }
         *reinterpret_cast<uint4*>(xs + ((fz * t.FY + fy) * t.FX + fx) * t.CiP + c8 * 8) = v;
     }
+    // after the tile: the LDS offset of every 8-channel chunk of the reduction
+    // index relative to a position's tap (0, 0, 0) voxel (-1: zero padding of
+    // K), then one chunk of zeros
+    const int tile = c.kd * t.FY * t.FX * t.CiP;
+    int* offs = reinterpret_cast<int*>(xs + tile);
+    const int nchunk = c.Kp / 8;
+    u16* zero = xs + tile + 2 * nchunk;
+    for (int j = threadIdx.x; j < nchunk; j += 256) {
+        int o = -1;
+        if (8 * j < c.K) {
+            const int4 tp = taps[j];  // (a, b, cc, ci) of this chunk
+            o = ((tp.x * t.FY + tp.y) * t.FX + tp.z) * t.CiP + tp.w;
+        }
+        offs[j] = o;
+    }
+    if (threadIdx.x == 0) *reinterpret_cast<uint4*>(zero) = make_uint4(0, 0, 0, 0);
     __syncthreads();
     const int pl = wave * 32 + (lane & 31);
     const int oyl = pl / c.Wo, ox = pl % c.Wo;
     const int oy = oy0 + oyl;
     const bool pon = oyl < t.TY && oy < c.Ho;
-    const int base = pon ? (oyl * c.sh * t.FX + ox * c.sw) * t.CiP : 0;
+    // positions past the tile read valid LDS; their outputs are not stored
+    const u16* xb = xs + (pon ? (oyl * c.sh * t.FX + ox * c.sw) * t.CiP : 0);
     const int co0 = blockIdx.y * 32;
-    const u16* wrow = w + (size_t)(co0 + (lane & 31)) * c.Kp;
+    const u16* wrow = w + (size_t)(co0 + (lane & 31)) * c.Kp + half * 8;
     f32x16 acc = {};
-    for (int k0 = 0; k0 < c.Kp; k0 += 16) {
-        const int kk = k0 + half * 8;
-        const uint4 av = *reinterpret_cast<const uint4*>(wrow + kk);
-        uint4 bv = make_uint4(0, 0, 0, 0);
-        if (kk < c.K && pon) {
-            const int4 tp = taps[kk / 8];  // (a, b, cc, ci) of this 8-channel chunk
-            bv = *reinterpret_cast<const uint4*>(
-                xs + base + ((tp.x * t.FY + tp.y) * t.FX + tp.z) * t.CiP + tp.w);
-        }
-        acc = mfma(av, bv, acc);
+    // four reduction steps per trip, all loads issued before the first MFMA
+    auto b_of = [&](int k0) {
+        const int o = offs[k0 / 8 + half];
+        return *reinterpret_cast<const uint4*>(o >= 0 ? xb + o : zero);
+    };
+    int k0 = 0;
+    for (; k0 + 64 <= c.Kp; k0 += 64) {
+        const uint4 a0 = *reinterpret_cast<const uint4*>(wrow + k0);
+        const uint4 a1 = *reinterpret_cast<const uint4*>(wrow + k0 + 16);
+        const uint4 a2 = *reinterpret_cast<const uint4*>(wrow + k0 + 32);
+        const uint4 a3 = *reinterpret_cast<const uint4*>(wrow + k0 + 48);
+        const uint4 b0 = b_of(k0), b1 = b_of(k0 + 16), b2 = b_of(k0 + 32), b3 = b_of(k0 + 48);
+        acc = mfma(a0, b0, acc);
+        acc = mfma(a1, b1, acc);
+        acc = mfma(a2, b2, acc);
+        acc = mfma(a3, b3, acc);
     }
+    for (; k0 < c.Kp; k0 += 16)
+        acc = mfma(*reinterpret_cast<const uint4*>(wrow + k0), b_of(k0), acc);
     if (!pon) return;
     const size_t p = (((size_t)n * c.Do + oz) * c.Ho + oy) * c.Wo + ox;
 #pragma unroll
@@ -552,7 +577,9 @@ FwdTile fwd_tile(const ConvGeo& c) {
 
 size_t fwd_lds_bytes(const ConvGeo& c) {
     const FwdTile t = fwd_tile(c);
-    return sizeof(u16) * (size_t)c.kd * t.FY * t.FX * t.CiP;
+    // input tile, chunk offsets (Kp / 8 ints), one zero chunk (16 bytes)
+    return sizeof(u16) * (size_t)c.kd * t.FY * t.FX * t.CiP + sizeof(int) * (size_t)(c.Kp / 8) +
+           16;
 }
 
 hipError_t conv_forward(const ConvGeo& c, const void* x, const void* w, const float* bias,
