@@ -269,12 +269,15 @@ struct AdjointArgs {
     float k0dz;
 };
 
-template <int NX, int NY>
-__global__ __launch_bounds__(kBlock) void adjoint_kernel(AdjointArgs a) {
+// BLK = threads per workgroup: 64 for fields of at most 512^2, so that a
+// small field still spreads over many CUs (a 256^2 field has 64 units of 4
+// rows instead of 16 of 16).
+template <int NX, int NY, int BLK>
+__global__ __launch_bounds__(BLK) void adjoint_kernel(AdjointArgs a) {
     extern __shared__ float2 smem[];
     const int G = gridDim.x, v = virtual_block();
-    const int rows_u = (a.ny + units_per_block<NX>() - 1) / units_per_block<NX>();
-    const int cols_u = (a.nx + units_per_block<NY>() - 1) / units_per_block<NY>();
+    const int rows_u = (a.ny + units_per_block<NX, BLK>() - 1) / units_per_block<NX, BLK>();
+    const int cols_u = (a.nx + units_per_block<NY, BLK>() - 1) / units_per_block<NY, BLK>();
     const size_t plane = (size_t)a.nx * a.ny;
     const int N = a.steps, K = a.K, C = (N + K - 1) / K;
     unsigned nbar = 0;
@@ -282,16 +285,16 @@ __global__ __launch_bounds__(kBlock) void adjoint_kernel(AdjointArgs a) {
     Twiddles<NX, kR> twx;
     Twiddles<NY, kR> twy;
     twx.load(a.twx, threadIdx.x % (NX / kR));
-    twy.load(a.twy, threadIdx.x / units_per_block<NY>());
+    twy.load(a.twy, threadIdx.x / units_per_block<NY, BLK>());
     float d[kR];
     for (int i = 0; i < kR; ++i) d[i] = 0.f;
 
     auto col_pass = [&](float2* work, bool conj, float2* spec_out) {
         for (int u = v; u < cols_u; u += G) {
             if (conj)
-                col_unit<NY, true>(u, a.nx, work, a.H, twy, smem, spec_out, a.permx, a.permy);
+                col_unit<NY, true, BLK>(u, a.nx, work, a.H, twy, smem, spec_out, a.permx, a.permy);
             else
-                col_unit<NY, false>(u, a.nx, work, a.H, twy, smem, nullptr, nullptr, nullptr);
+                col_unit<NY, false, BLK>(u, a.nx, work, a.H, twy, smem, nullptr, nullptr, nullptr);
         }
     };
 
@@ -299,7 +302,7 @@ __global__ __launch_bounds__(kBlock) void adjoint_kernel(AdjointArgs a) {
     if (C > 1) {
         RowArgs ra{a.field_in, a.fwork, nullptr, nullptr, nullptr, nullptr, nullptr, a.k0dz};
         for (int u = v; u < rows_u; u += G)
-            row_unit<NX, kNaturalIn, kNoOps, kSpecOut>(u, a.ny, ra, d, twx, smem);
+            row_unit<NX, kNaturalIn, kNoOps, kSpecOut, BLK>(u, a.ny, ra, d, twx, smem);
         ra.src = a.fwork;
         const int last = (C - 1) * K;
         for (int j = 0; j < last; ++j) {
@@ -308,11 +311,11 @@ __global__ __launch_bounds__(kBlock) void adjoint_kernel(AdjointArgs a) {
             grid_sync(a.counter, ++nbar, abort);
             ra.keep = ((j + 1) % K == 0) ? a.ckpt + (size_t)((j + 1) / K) * plane : nullptr;
             for (int u = v; u < rows_u; u += G) {
-                load_dn<NX>(d, u, a.ny, a.dn + j * plane);
+                load_dn<NX, BLK>(d, u, a.ny, a.dn + j * plane);
                 if (j + 1 < last)
-                    row_unit<NX, kSpecIn, kScreen, kSpecOut>(u, a.ny, ra, d, twx, smem);
+                    row_unit<NX, kSpecIn, kScreen, kSpecOut, BLK>(u, a.ny, ra, d, twx, smem);
                 else
-                    row_unit<NX, kSpecIn, kScreen, kNoOut>(u, a.ny, ra, d, twx, smem);
+                    row_unit<NX, kSpecIn, kScreen, kNoOut, BLK>(u, a.ny, ra, d, twx, smem);
             }
         }
     }
@@ -324,7 +327,7 @@ __global__ __launch_bounds__(kBlock) void adjoint_kernel(AdjointArgs a) {
         RowArgs fr{c == 0 ? a.field_in : a.ckpt + (size_t)c * plane, a.fwork, nullptr, nullptr,
                    nullptr, nullptr, nullptr, a.k0dz};
         for (int u = v; u < rows_u; u += G)
-            row_unit<NX, kNaturalIn, kNoOps, kSpecOut>(u, a.ny, fr, d, twx, smem);
+            row_unit<NX, kNaturalIn, kNoOps, kSpecOut, BLK>(u, a.ny, fr, d, twx, smem);
         fr.src = a.fwork;
         for (int s = 0; s < L; ++s) {
             grid_sync(a.counter, ++nbar, abort);
@@ -332,11 +335,11 @@ __global__ __launch_bounds__(kBlock) void adjoint_kernel(AdjointArgs a) {
             grid_sync(a.counter, ++nbar, abort);
             fr.keep = a.seg + (size_t)s * plane;
             for (int u = v; u < rows_u; u += G) {
-                load_dn<NX>(d, u, a.ny, a.dn + (start + s) * plane);
+                load_dn<NX, BLK>(d, u, a.ny, a.dn + (start + s) * plane);
                 if (s + 1 < L)
-                    row_unit<NX, kSpecIn, kScreen, kSpecOut>(u, a.ny, fr, d, twx, smem);
+                    row_unit<NX, kSpecIn, kScreen, kSpecOut, BLK>(u, a.ny, fr, d, twx, smem);
                 else
-                    row_unit<NX, kSpecIn, kScreen, kNoOut>(u, a.ny, fr, d, twx, smem);
+                    row_unit<NX, kSpecIn, kScreen, kNoOut, BLK>(u, a.ny, fr, d, twx, smem);
             }
         }
         for (int s = L - 1; s >= 0; --s) {
@@ -346,14 +349,14 @@ __global__ __launch_bounds__(kBlock) void adjoint_kernel(AdjointArgs a) {
                        a.k0dz};
             grid_sync(a.counter, ++nbar, abort);
             for (int u = v; u < rows_u; u += G) {
-                load_dn<NX>(d, u, a.ny, a.dn + j * plane);
+                load_dn<NX, BLK>(d, u, a.ny, a.dn + j * plane);
                 if (j + 1 < N) {
-                    row_unit<NX, kSpecIn, kAdjointOps, kSpecOut>(u, a.ny, br, d, twx, smem);
+                    row_unit<NX, kSpecIn, kAdjointOps, kSpecOut, BLK>(u, a.ny, br, d, twx, smem);
                 } else if (a.gout) {
                     br.src = a.gout;
-                    row_unit<NX, kNaturalIn, kAdjointOps, kSpecOut>(u, a.ny, br, d, twx, smem);
+                    row_unit<NX, kNaturalIn, kAdjointOps, kSpecOut, BLK>(u, a.ny, br, d, twx, smem);
                 } else {
-                    row_unit<NX, kZeroIn, kAdjointOps, kSpecOut>(u, a.ny, br, d, twx, smem);
+                    row_unit<NX, kZeroIn, kAdjointOps, kSpecOut, BLK>(u, a.ny, br, d, twx, smem);
                 }
             }
             grid_sync(a.counter, ++nbar, abort);
@@ -366,7 +369,7 @@ __global__ __launch_bounds__(kBlock) void adjoint_kernel(AdjointArgs a) {
         grid_sync(a.counter, ++nbar, abort);
         RowArgs tr{a.gwork, a.gin, nullptr, nullptr, nullptr, nullptr, nullptr, a.k0dz};
         for (int u = v; u < rows_u; u += G)
-            row_unit<NX, kSpecIn, kNoOps, kNaturalOut>(u, a.ny, tr, d, twx, smem);
+            row_unit<NX, kSpecIn, kNoOps, kNaturalOut, BLK>(u, a.ny, tr, d, twx, smem);
     }
 }
 
@@ -474,17 +477,17 @@ static int device_cus() {
     return cus;
 }
 
-template <int NX, int NY>
+template <int NX, int NY, int BLK = kBlock>
 static size_t persistent_lds() {
-    const size_t lds_r = sizeof(float2) * units_per_block<NX>() * lds_size<NX>();
-    const size_t lds_c = sizeof(float2) * units_per_block<NY>() * lds_size<NY>();
+    const size_t lds_r = sizeof(float2) * units_per_block<NX, BLK>() * lds_size<NX>();
+    const size_t lds_c = sizeof(float2) * units_per_block<NY, BLK>() * lds_size<NY>();
     return lds_r > lds_c ? lds_r : lds_c;
 }
 
-template <int NX, int NY>
+template <int NX, int NY, int BLK = kBlock>
 static int persistent_grid(int nx, int ny, int fields = 1, int per_cu = 1) {
-    const int rows_u = (ny + units_per_block<NX>() - 1) / units_per_block<NX>();
-    const int cols_u = (nx + units_per_block<NY>() - 1) / units_per_block<NY>();
+    const int rows_u = (ny + units_per_block<NX, BLK>() - 1) / units_per_block<NX, BLK>();
+    const int cols_u = (nx + units_per_block<NY, BLK>() - 1) / units_per_block<NY, BLK>();
     const int cus = device_cus() * per_cu;
     const int grid = (rows_u > cols_u ? rows_u : cols_u) * fields;
     return grid > cus ? cus : grid;
@@ -587,11 +590,12 @@ hipError_t launch_adjoint(const Geom& g, const Plan& p, const AdjointIO& io, int
                   g.steps, K, k0dz_of(g)};
     return dispatch2(g.nx, g.ny, [&](auto xc, auto yc) {
         constexpr int NX = decltype(xc)::value, NY = decltype(yc)::value;
+        constexpr int BLK = NX <= 512 && NY <= 512 ? 64 : kBlock;
         void* args[] = {&a};
-        return hipLaunchCooperativeKernel(reinterpret_cast<const void*>(&adjoint_kernel<NX, NY>),
-                                          dim3(persistent_grid<NX, NY>(g.nx, g.ny)),
-                                          dim3(kBlock), args, (unsigned)persistent_lds<NX, NY>(),
-                                          s);
+        return hipLaunchCooperativeKernel(
+            reinterpret_cast<const void*>(&adjoint_kernel<NX, NY, BLK>),
+            dim3(persistent_grid<NX, NY, BLK>(g.nx, g.ny)), dim3(BLK), args,
+            (unsigned)persistent_lds<NX, NY, BLK>(), s);
     });
 }
 

@@ -16,8 +16,9 @@ constexpr int kR = 16;           // complex values per thread
 constexpr int kBlock = 256;      // threads per workgroup
 constexpr int kBarWords = 1024;  // grid-barrier words (4 KiB) in the plan
 
-template <int N>
-constexpr int units_per_block() { return kBlock / (N / kR); }
+// rows (or columns) of length N one workgroup of BLK threads transforms at once
+template <int N, int BLK = kBlock>
+constexpr int units_per_block() { return BLK / (N / kR); }
 
 // calls f(std::integral_constant<int, n>{}) for a supported transform length n
 template <typename F>
@@ -92,10 +93,10 @@ __device__ __forceinline__ void apply_screen(float2 (&v)[kR], const float (&ph)[
 }
 
 // dn of this thread's row unit, fetched ahead of the row pass
-template <int NX>
+template <int NX, int BLK = kBlock>
 __device__ __forceinline__ void load_dn(float (&d)[kR], int unit, int ny,
                                         const float* __restrict__ dn) {
-    constexpr int T = NX / kR, B = units_per_block<NX>();
+    constexpr int T = NX / kR, B = units_per_block<NX, BLK>();
     const int row = unit * B + threadIdx.x / T, tau = threadIdx.x % T;
     const size_t rowoff = (size_t)(row < ny ? row : 0) * NX;
 #pragma unroll
@@ -121,9 +122,9 @@ struct RowArgs {
 // A row unit's field values (kSpecIn: spectrum, kNaturalIn: natural order);
 // split from the computation so that a workgroup can issue the loads of its
 // next unit before it works on the current one.
-template <int NX, int IN>
+template <int NX, int IN, int BLK = kBlock>
 __device__ __forceinline__ void row_load(int unit, int ny, const float2* src, float2 (&v)[kR]) {
-    constexpr int T = NX / kR, B = units_per_block<NX>();
+    constexpr int T = NX / kR, B = units_per_block<NX, BLK>();
     const int row = unit * B + threadIdx.x / T, tau = threadIdx.x % T;
     const size_t rowoff = (size_t)(row < ny ? row : 0) * NX;
     if constexpr (IN == kZeroIn) {
@@ -135,11 +136,11 @@ __device__ __forceinline__ void row_load(int unit, int ny, const float2* src, fl
     }
 }
 
-template <int NX, int IN, int OPS, int OUT, typename Tw>
+template <int NX, int IN, int OPS, int OUT, int BLK = kBlock, typename Tw>
 __device__ __forceinline__ void row_body(int unit, int ny, const RowArgs& a,
                                          const float (&d)[kR], const Tw& twx, float2* smem,
                                          float2 (&v)[kR]) {
-    constexpr int T = NX / kR, B = units_per_block<NX>();
+    constexpr int T = NX / kR, B = units_per_block<NX, BLK>();
     const int sub = threadIdx.x / T, tau = threadIdx.x % T;
     const int row = unit * B + sub;
     const bool on = row < ny;
@@ -195,22 +196,22 @@ __device__ __forceinline__ void row_body(int unit, int ny, const RowArgs& a,
     }
 }
 
-template <int NX, int IN, int OPS, int OUT, typename Tw>
+template <int NX, int IN, int OPS, int OUT, int BLK = kBlock, typename Tw>
 __device__ __forceinline__ void row_unit(int unit, int ny, const RowArgs& a,
                                          const float (&d)[kR], const Tw& twx, float2* smem) {
     float2 v[kR];
-    row_load<NX, IN>(unit, ny, a.src, v);
-    row_body<NX, IN, OPS, OUT>(unit, ny, a, d, twx, smem, v);
+    row_load<NX, IN, BLK>(unit, ny, a.src, v);
+    row_body<NX, IN, OPS, OUT, BLK>(unit, ny, a, d, twx, smem, v);
 }
 
 // Column pass on a working buffer: forward column FFTs, x H (or conj(H)),
 // inverse column FFTs.  With spec_out, the multiplied spectrum is also written
 // to spec_out in natural DFT order (the pupil-plane gradient).
-template <int NY>
+template <int NY, int BLK = kBlock>
 __device__ __forceinline__ void col_load(int unit, int nx, const float2* work,
                                          const float2* __restrict__ H, float2 (&v)[kR],
                                          float2 (&h)[kR]) {
-    constexpr int T = NY / kR, W = units_per_block<NY>();
+    constexpr int T = NY / kR, W = units_per_block<NY, BLK>();
     const int c = unit * W + threadIdx.x % W, t = threadIdx.x / W;
     const size_t col = c < nx ? (size_t)c : 0;
 #pragma unroll
@@ -219,13 +220,13 @@ __device__ __forceinline__ void col_load(int unit, int nx, const float2* work,
     for (int r = 0; r < kR; ++r) h[r] = H[(size_t)(r * T + t) * nx + col];
 }
 
-template <int NY, bool CONJ, typename Tw>
+template <int NY, bool CONJ, int BLK = kBlock, typename Tw>
 __device__ __forceinline__ void col_body(int unit, int nx, float2* work, const Tw& twy,
                                          float2* smem,
                                          float2* spec_out, const int* __restrict__ permx,
                                          const int* __restrict__ permy, float2 (&v)[kR],
                                          const float2 (&h)[kR]) {
-    constexpr int T = NY / kR, W = units_per_block<NY>();
+    constexpr int T = NY / kR, W = units_per_block<NY, BLK>();
     const int w = threadIdx.x % W, t = threadIdx.x / W;
     const int c = unit * W + w;
     const bool on = c < nx;
@@ -247,15 +248,15 @@ __device__ __forceinline__ void col_body(int unit, int nx, float2* work, const T
     }
 }
 
-template <int NY, bool CONJ, typename Tw>
+template <int NY, bool CONJ, int BLK = kBlock, typename Tw>
 __device__ __forceinline__ void col_unit(int unit, int nx, float2* work,
                                          const float2* __restrict__ H, const Tw& twy,
                                          float2* smem,
                                          float2* spec_out, const int* __restrict__ permx,
                                          const int* __restrict__ permy) {
     float2 v[kR], h[kR];
-    col_load<NY>(unit, nx, work, H, v, h);
-    col_body<NY, CONJ>(unit, nx, work, twy, smem, spec_out, permx, permy, v, h);
+    col_load<NY, BLK>(unit, nx, work, H, v, h);
+    col_body<NY, CONJ, BLK>(unit, nx, work, twy, smem, spec_out, permx, permy, v, h);
 }
 
 // ---------------------------------------------------------------------------
