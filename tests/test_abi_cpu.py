@@ -146,3 +146,67 @@ def test_helper_validation(L):
     assert L.bpm_pupil_spectrum(b.p, b.p, 64, 64, 0.2, 0.5, 1.33, float("nan"), b.p, None) == \
         B.BPM_ERR_NOT_FINITE
     assert L.bpm_pupil_phase_grad(None, b.p, 64, 64, b.p, None) == B.BPM_ERR_INVALID_ARG
+
+
+def test_surrogate_validation(L):
+    from paper_1706_02261_amd import _lib as B
+    b = Buf(1 << 16)
+    # sizes are pure host arithmetic
+    assert L.psf_surrogate_param_count() > 0
+    assert L.psf_surrogate_weights_bytes() % 256 == 0
+    assert L.psf_surrogate_workspace_size(1, 1) > L.psf_surrogate_workspace_size(1, 0)
+    assert L.psf_surrogate_workspace_size(-1, 0) == 0
+    g = (ctypes.c_int * 15)()
+    assert L.psf_surrogate_layer_geometry(0, g) == B.BPM_OK and list(g)[:6] == [1, 64, 32, 32, 8, 32]
+    assert L.psf_surrogate_layer_geometry(6, g) == B.BPM_ERR_INVALID_ARG
+    nbytes = L.psf_surrogate_weights_bytes()
+    # wrong blob size, negative batch, missing workspace
+    assert L.psf_surrogate_infer(b.p, nbytes - 1, b.p, b.p, 4, b.p, b.p, b.p, 1 << 20,
+                                 None) == B.BPM_ERR_INVALID_ARG
+    assert L.psf_surrogate_infer(b.p, nbytes, b.p, b.p, -1, b.p, b.p, b.p, 1 << 20,
+                                 None) == B.BPM_ERR_INVALID_ARG
+    assert L.psf_surrogate_infer(b.p, nbytes, b.p, b.p, 0, None, None, None, 0, None) == B.BPM_OK
+    assert L.psf_surrogate_infer(b.p, nbytes, b.p, b.p, 4, b.p, b.p, b.p, 16,
+                                 None) == B.BPM_ERR_WORKSPACE
+    # training step: batch range, lr, step
+    ws = L.psf_surrogate_workspace_size(8, 1)
+    assert L.psf_surrogate_train_step(b.p, b.p, b.p, b.p, 0, 1e-3, 1.0, 1, b.p, None, b.p, ws,
+                                      None) == B.BPM_ERR_INVALID_ARG
+    assert L.psf_surrogate_train_step(b.p, b.p, b.p, b.p, 8, float("nan"), 1.0, 1, b.p, None,
+                                      b.p, ws, None) == B.BPM_ERR_NOT_FINITE
+    assert L.psf_surrogate_train_step(b.p, b.p, b.p, b.p, 8, 1e-3, 1.0, 0, b.p, None, b.p, ws,
+                                      None) == B.BPM_ERR_INVALID_ARG
+    # patch extraction: the 64-slice window must fit
+    assert L.psf_extract_patches(b.p, 63, 32, 32, 0, b.p, 1, b.p, None) == B.BPM_ERR_INVALID_ARG
+    assert L.psf_extract_patches(b.p, 70, 32, 32, 7, b.p, 1, b.p, None) == B.BPM_ERR_INVALID_ARG
+    assert L.psf_extract_patches(b.p, 70, 32, 32, 6, b.p, 0, b.p, None) == B.BPM_OK
+
+
+@pytest.mark.parametrize("geom,code", [
+    ((1, 8, 8, 8, 6, 32, 3, 3, 3, 1, 1, 1, 1, 1, 1), "unsupported"),   # Ci not a multiple of 8
+    ((1, 8, 8, 8, 8, 48, 3, 3, 3, 1, 1, 1, 1, 1, 1), "unsupported"),   # Co not 32 .. 256
+    ((1, 8, 8, 8, 8, 32, 9, 3, 3, 1, 1, 1, 0, 1, 1), "invalid"),       # kernel larger than input
+    ((1, 4, 4, 300, 8, 32, 1, 1, 1, 1, 1, 1, 0, 0, 0), "unsupported"),  # output rows over 128
+    ((0, 8, 8, 8, 8, 32, 3, 3, 3, 1, 1, 1, 1, 1, 1), "invalid"),
+])
+def test_conv_geometry_validation(L, geom, code):
+    from paper_1706_02261_amd import _lib as B
+    b = Buf(1 << 16)
+    g = (ctypes.c_int * 15)(*geom)
+    want = B.BPM_ERR_UNSUPPORTED_SIZE if code == "unsupported" else B.BPM_ERR_INVALID_ARG
+    assert L.psf_conv_forward(b.p, b.p, b.p, g, 0, b.p, None, None, b.p, 1 << 16, None) == want
+
+
+def test_point_sources_validation(L):
+    from paper_1706_02261_amd import _lib as B
+    b = Buf()
+    ws = L.bpm_point_sources_workspace_size(64, 64)
+    assert ws > 0 and L.bpm_point_sources_workspace_size(48, 64) == 0
+    assert L.bpm_point_sources(b.p, None, 4, 64, 64, 0.2, 0.5, 1.33, 0.0, 0.0, b.p, b.p, ws,
+                               None) == B.BPM_ERR_NOT_FINITE
+    assert L.bpm_point_sources(b.p, None, -1, 64, 64, 0.2, 0.5, 1.33, 0.6, 0.0, b.p, b.p, ws,
+                               None) == B.BPM_ERR_INVALID_ARG
+    assert L.bpm_point_sources(None, None, 4, 64, 64, 0.2, 0.5, 1.33, 0.6, 0.0, b.p, b.p, ws,
+                               None) == B.BPM_ERR_INVALID_ARG
+    assert L.bpm_point_sources(b.p, None, 4, 64, 64, 0.2, 0.5, 1.33, 0.6, 0.0, b.p, b.p, 8,
+                               None) == B.BPM_ERR_WORKSPACE
