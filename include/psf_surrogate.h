@@ -85,7 +85,8 @@ int psf_surrogate_export(const void* state, void* weights_blob, void* hip_stream
  *   patches[s][z][y][x] = dn[z0 + z][(sy - 16 + y) mod ny][(sx - 16 + x) mod nx]
  * for z < 64, y, x < 32, with (sy, sx) = sources[s] (device int32 [n][2]) --
  * the same window as a 32 x 32 PSF crop of bpm_psf_readout.  dn: device
- * float32 [nz][ny][nx] with z0 + 64 <= nz; patches: device float32 [n][64][32][32]. */
+ * float32 [nz][ny][nx] with ny, nx >= 32 and z0 + 64 <= nz; patches: device
+ * float32 [n][64][32][32], 16-byte aligned. */
 int psf_extract_patches(const float* dn, int nz, int ny, int nx, int z0, const int* sources,
                         int n, float* patches, void* hip_stream);
 

@@ -54,22 +54,37 @@ __device__ __forceinline__ bool source_mode(const SourceSpec& q, long e, double*
     return true;
 }
 
-// one block: sum_k |S(k)|^2 in double
-__global__ void source_norm_kernel(SourceSpec q, double* out) {
-    __shared__ double part[1024];
+// sum_k |S(k)|^2 in double: kNormBlocks partial sums, then one block adds
+// them in a fixed order (deterministic)
+constexpr int kNormBlocks = 256;
+
+__global__ void source_norm_partial_kernel(SourceSpec q, double* __restrict__ part) {
+    __shared__ double red[256];
     const long n = (long)q.nx * q.ny;
     double s = 0.0;
-    for (long e = threadIdx.x; e < n; e += blockDim.x) {
+    for (long e = blockIdx.x * (long)blockDim.x + threadIdx.x; e < n;
+         e += (long)gridDim.x * blockDim.x) {
         double amp, kz;
         if (source_mode(q, e, &amp, &kz)) s += amp * amp;
     }
-    part[threadIdx.x] = s;
+    red[threadIdx.x] = s;
     __syncthreads();
     for (int st = blockDim.x / 2; st > 0; st >>= 1) {
-        if ((int)threadIdx.x < st) part[threadIdx.x] += part[threadIdx.x + st];
+        if ((int)threadIdx.x < st) red[threadIdx.x] += red[threadIdx.x + st];
         __syncthreads();
     }
-    if (threadIdx.x == 0) out[0] = part[0];
+    if (threadIdx.x == 0) part[blockIdx.x] = red[0];
+}
+
+__global__ void source_norm_final_kernel(const double* __restrict__ part, double* out) {
+    __shared__ double red[kNormBlocks];
+    red[threadIdx.x] = part[threadIdx.x];
+    __syncthreads();
+    for (int st = kNormBlocks / 2; st > 0; st >>= 1) {
+        if ((int)threadIdx.x < st) red[threadIdx.x] += red[threadIdx.x + st];
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) out[0] = red[0];
 }
 
 // C[k] <- C[k] S(k) / ||u_src||
@@ -92,7 +107,8 @@ __global__ void source_apply_kernel(SourceSpec q, const double* __restrict__ nor
 }
 
 size_t sources_bytes(int nx, int ny) {
-    return plan_bytes(nx, ny) + align_up(sizeof(float2) * (size_t)nx * ny) + kAlign;
+    return plan_bytes(nx, ny) + align_up(sizeof(float2) * (size_t)nx * ny) + kAlign +
+           align_up(sizeof(double) * kNormBlocks);
 }
 
 hipError_t launch_point_sources(const SourceArgs& a, void* ws, hipStream_t s) {
@@ -103,6 +119,8 @@ hipError_t launch_point_sources(const SourceArgs& a, void* ws, hipStream_t s) {
     float2* comb = (float2*)b;
     b += align_up(sizeof(float2) * n);
     double* norm2 = (double*)b;
+    b += kAlign;
+    double* partial = (double*)b;
     const Geom g{a.nx, a.ny, 0, a.dx, 0.0, a.wavelength, a.n0};
     hipError_t e = launch_plan(g, p, false, s);
     if (e != hipSuccess) return e;
@@ -125,7 +143,8 @@ hipError_t launch_point_sources(const SourceArgs& a, void* ws, hipStream_t s) {
     q.pthr = (double)a.nx * (double)a.ny * a.na * a.dx / a.wavelength;
     q.pthr *= q.pthr;
     q.z_d = a.z_d;
-    source_norm_kernel<<<1, 1024, 0, s>>>(q, norm2);
+    source_norm_partial_kernel<<<kNormBlocks, 256, 0, s>>>(q, partial);
+    source_norm_final_kernel<<<1, kNormBlocks, 0, s>>>(partial, norm2);
     source_apply_kernel<<<blocks, 256, 0, s>>>(q, norm2, comb);
     e = hipGetLastError();
     if (e == hipSuccess)

@@ -364,17 +364,26 @@ __global__ void prep_input_kernel(const float* __restrict__ dn, const float* __r
 }
 
 // patches[s][z][y][x] = dn[z0 + z][(sy - 16 + y) mod ny][(sx - 16 + x) mod nx]
+// grid (64, sources): 64 blocks of 256 threads per patch, four consecutive x
+// per thread (one 16-byte store)
 __global__ void extract_kernel(const float* __restrict__ dn, int ny, int nx, int z0,
-                               const int* __restrict__ src, long total, float* __restrict__ out) {
-    for (long e = blockIdx.x * (long)blockDim.x + threadIdx.x; e < total;
-         e += (long)gridDim.x * blockDim.x) {
-        const long s = e / (64 * 32 * 32);
-        const int r = (int)(e % (64 * 32 * 32));
-        const int z = r / 1024, y = r / 32 % 32, x = r % 32;
-        const int gy = ((src[2 * s] - 16 + y) % ny + ny) % ny;
-        const int gx = ((src[2 * s + 1] - 16 + x) % nx + nx) % nx;
-        out[e] = dn[((size_t)(z0 + z) * ny + gy) * nx + gx];
+                               const int* __restrict__ src, int s0, float* __restrict__ out) {
+    const int s = s0 + blockIdx.y;
+    const int sy = ((src[2 * s] % ny) + ny) % ny, sx = ((src[2 * s + 1] % nx) + nx) % nx;
+    const int e = (blockIdx.x * blockDim.x + threadIdx.x) * 4;  // < 64 * 32 * 32
+    const int z = e >> 10, y = (e >> 5) & 31, x = e & 31;
+    int gy = sy - 16 + y;
+    gy += gy < 0 ? ny : (gy >= ny ? -ny : 0);
+    const float* row = dn + ((size_t)(z0 + z) * ny + gy) * nx;
+    float v[4];
+#pragma unroll
+    for (int i = 0; i < 4; ++i) {
+        int gx = sx - 16 + x + i;
+        gx += gx < 0 ? nx : (gx >= nx ? -nx : 0);
+        v[i] = row[gx];
     }
+    *reinterpret_cast<float4*>(out + (size_t)s * (64 * 32 * 32) + e) =
+        make_float4(v[0], v[1], v[2], v[3]);
 }
 
 // nearest-neighbour x2 upsampling of [N][h][w][C] (bf16)
@@ -639,9 +648,13 @@ hipError_t prep_input(const float* dn, const float* depth, int B, void* x0, hipS
 
 hipError_t extract_patches(const float* dn, int ny, int nx, int z0, const int* src, int n,
                            float* out, hipStream_t s) {
-    const long total = (long)n * 64 * 32 * 32;
-    extract_kernel<<<grid_for(total), 256, 0, s>>>(dn, ny, nx, z0, src, total, out);
-    return hipGetLastError();
+    for (int s0 = 0; s0 < n; s0 += 65535) {
+        const int m = n - s0 < 65535 ? n - s0 : 65535;
+        extract_kernel<<<dim3(64, m), 256, 0, s>>>(dn, ny, nx, z0, src, s0, out);
+        const hipError_t e = hipGetLastError();
+        if (e != hipSuccess) return e;
+    }
+    return hipSuccess;
 }
 
 hipError_t upsample(const void* a, int N, int h, int w, int C, void* u, hipStream_t s) {

@@ -516,15 +516,16 @@ int psf_surrogate_infer(const void* weights_bf16, size_t weights_bytes, const fl
 
 int psf_extract_patches(const float* dn, int nz, int ny, int nx, int z0, const int* sources,
                         int n, float* patches, void* hip_stream) {
-    if (nz < 1 || ny < 1 || nx < 1 || z0 < 0 || z0 + kPatchD > nz)
-        return fail(BPM_ERR_INVALID_ARG, "nz=%d ny=%d nx=%d z0=%d: need z0 + %d <= nz", nz, ny,
-                    nx, z0, kPatchD);
+    if (ny < kPatchHW || nx < kPatchHW || z0 < 0 || z0 + kPatchD > nz)
+        return fail(BPM_ERR_INVALID_ARG,
+                    "nz=%d ny=%d nx=%d z0=%d: need ny, nx >= %d and z0 + %d <= nz", nz, ny, nx,
+                    z0, kPatchHW, kPatchD);
     if ((double)nz * ny * nx > 4e10) return fail(BPM_ERR_UNSUPPORTED_SIZE, "dn volume too large");
     if (n < 0) return fail(BPM_ERR_INVALID_ARG, "n=%d must be >= 0", n);
     if (n == 0) return BPM_OK;
     if (int rc = check_ptr(dn, 4, "dn")) return rc;
     if (int rc = check_ptr(sources, 4, "sources")) return rc;
-    if (int rc = check_ptr(patches, 4, "patches")) return rc;
+    if (int rc = check_ptr(patches, 16, "patches")) return rc;
     return device_status(sg::extract_patches(dn, ny, nx, z0, sources, n, patches,
                                              static_cast<hipStream_t>(hip_stream)),
                          "extract patches");
