@@ -116,8 +116,8 @@ BatchLayout batch_layout(const bpm_job* jobs, int n) {
         const int P = batch_passes(jobs[i]);
         L.n_segs += P;
         const long items = jobs[i].steps > 0
-            ? (long)bpm::row_units(jobs[i].nx, jobs[i].ny) * (jobs[i].steps + 1) +
-              (long)bpm::col_units(jobs[i].nx, jobs[i].ny) * jobs[i].steps
+            ? (long)bpm::row_items(jobs[i].nx, jobs[i].ny) * (jobs[i].steps + 1) +
+              (long)bpm::col_items(jobs[i].nx, jobs[i].ny) * jobs[i].steps
             : 0;
         L.n_items += (int)items;
     }
@@ -143,8 +143,8 @@ int check_batch(const bpm_job* jobs, int n) {
         if (j.intensity_out && !aligned(j.intensity_out, 4))
             return fail(BPM_ERR_INVALID_ARG, "job %d: intensity_out must be 4-byte aligned", i);
         if (j.steps > 0)
-            items += (long)bpm::row_units(j.nx, j.ny) * (j.steps + 1) +
-                     (long)bpm::col_units(j.nx, j.ny) * j.steps;
+            items += (long)bpm::row_items(j.nx, j.ny) * (j.steps + 1) +
+                     (long)bpm::col_items(j.nx, j.ny) * j.steps;
     }
     if (items >= (1L << 31)) return fail(BPM_ERR_INVALID_ARG, "batch has too many work items");
     return BPM_OK;
@@ -229,8 +229,8 @@ int bpm_propagate_batch(const bpm_job* jobs, int n_jobs, void* workspace,
     for (int r = 0; r < maxP; ++r) {
         for (int i : order) {
             if (r >= batch_passes(jobs[i])) continue;
-            const int R = bpm::row_units(jobs[i].nx, jobs[i].ny);
-            const int C = bpm::col_units(jobs[i].nx, jobs[i].ny);
+            const int R = bpm::row_items(jobs[i].nx, jobs[i].ny);
+            const int C = bpm::col_items(jobs[i].nx, jobs[i].ny);
             const int count = (r % 2 == 0) ? R : C;
             const int need = r == 0 ? 0 : R + (r / 2) * C + ((r - 1) / 2) * R;
             segs.push_back(bpm::BatchSeg{i, r, first, count, need});

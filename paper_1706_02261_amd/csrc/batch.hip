@@ -1,7 +1,7 @@
 // Uneven batch of independent marches in one persistent launch.
 //
-// The work of every job is cut into items: one item is one unit (a few rows
-// or columns) of one pass of one job.  The passes of job j are numbered
+// The work of every job is cut into items: one item is up to two units (a few
+// rows or columns each) of one pass of one job.  The passes of job j are numbered
 //   0          head row pass (forward row FFTs of u_0)
 //   2s + 1     column pass of step s
 //   2s + 2     row pass of step s (mid, or tail for the last step)
@@ -21,6 +21,13 @@
 
 namespace bpm {
 
+// Register twiddles whose transforms hide the thread index from the compiler
+// (see LdsTwiddles), so that their LDS addresses are recomputed per call.
+template <int N, int R>
+struct OpaqueTwiddles : Twiddles<N, R> {
+    static constexpr bool kOpaqueIndex = true;
+};
+
 // queue words: [0] next item, [16] time-out flag, [32 * (j + 1)] completed
 // items of job j
 __global__ void batch_zero_kernel(unsigned* q, int words) {
@@ -28,41 +35,88 @@ __global__ void batch_zero_kernel(unsigned* q, int words) {
         q[i] = 0u;
 }
 
+// One item covers up to kUnitsPerItem consecutive units of one pass: the
+// second unit's loads are issued before the first unit is transformed, and
+// the queue and completion-counter round trips are shared.
+// The per-size bodies are separate functions (not inlined into the item loop):
+// with every transform length inlined into one kernel the compiler keeps each
+// length's loop-invariant addresses live at once and spills.  Their pointer
+// parameters carry the address spaces (LDS, global) so that the bodies still
+// use LDS and global instructions.
+typedef __attribute__((address_space(3))) float2 lds_float2;
+typedef __attribute__((address_space(1))) float2 g_float2;
+typedef __attribute__((address_space(1))) float g_float;
+
 template <int NX>
-__device__ __forceinline__ void batch_row(const BatchJob& jb, int pass, int tile, float2* smem) {
-    Twiddles<NX, kR> tw;
-    tw.load((const float2*)jb.twx, threadIdx.x % (NX / kR));
-    float d[kR];
-#pragma unroll
-    for (int i = 0; i < kR; ++i) d[i] = 0.f;
+__device__ __attribute__((noinline)) void batch_row(const g_float2* field_in, g_float2* work_g,
+                                                    const g_float* dn, g_float* inten,
+                                                    const g_float2* twx, int nx, int ny,
+                                                    int steps, float k0dz, int pass, int item,
+                                                    lds_float2* lds) {
+    float2* smem = (float2*)lds;
+    float2* work = (float2*)work_g;
+    OpaqueTwiddles<NX, kR> tw;
+    tw.load((const float2*)twx, threadIdx.x % (NX / kR));
+    const int units = (ny + units_per_block<NX>() - 1) / units_per_block<NX>();
+    const int u0 = item * kUnitsPerItem, u1 = u0 + 1;
+    const bool two = u1 < units;
+    float d0[kR], d1[kR];
+    float2 va[kR], vb[kR];
     if (pass == 0) {
-        RowArgs ra{(const float2*)jb.field_in, (float2*)jb.work, nullptr, nullptr, nullptr, nullptr, nullptr, jb.k0dz};
-        row_unit<NX, kNaturalIn, kNoOps, kSpecOut>(tile, jb.ny, ra, d, tw, smem);
+#pragma unroll
+        for (int i = 0; i < kR; ++i) d0[i] = 0.f;
+        const RowArgs ra{(const float2*)field_in, work, nullptr, nullptr, nullptr, nullptr,
+                         nullptr, k0dz};
+        row_load<NX, kNaturalIn>(u0, ny, ra.src, va);
+        if (two) row_load<NX, kNaturalIn>(u1, ny, ra.src, vb);
+        row_body<NX, kNaturalIn, kNoOps, kSpecOut>(u0, ny, ra, d0, tw, smem, va);
+        if (two) row_body<NX, kNaturalIn, kNoOps, kSpecOut>(u1, ny, ra, d0, tw, smem, vb);
         return;
     }
     const int s = pass / 2 - 1;
-    const size_t plane = (size_t)jb.nx * jb.ny;
-    load_dn<NX>(d, tile, jb.ny, jb.dn + s * plane);
-    RowArgs ra{(const float2*)jb.work, (float2*)jb.work, jb.inten ? jb.inten + s * plane : nullptr, nullptr, nullptr,
-               nullptr, nullptr, jb.k0dz};
-    if (s + 1 < jb.steps)
-        row_unit<NX, kSpecIn, kScreen, kSpecOut>(tile, jb.ny, ra, d, tw, smem);
-    else
-        row_unit<NX, kSpecIn, kScreen, kNaturalOut>(tile, jb.ny, ra, d, tw, smem);
+    const size_t plane = (size_t)nx * ny;
+    const float* dns = (const float*)dn + s * plane;
+    const RowArgs ra{work, work, inten ? (float*)inten + s * plane : nullptr, nullptr, nullptr,
+                     nullptr, nullptr, k0dz};
+    row_load<NX, kSpecIn>(u0, ny, ra.src, va);
+    load_dn<NX>(d0, u0, ny, dns);
+    if (two) {
+        row_load<NX, kSpecIn>(u1, ny, ra.src, vb);
+        load_dn<NX>(d1, u1, ny, dns);
+    }
+    if (s + 1 < steps) {
+        row_body<NX, kSpecIn, kScreen, kSpecOut>(u0, ny, ra, d0, tw, smem, va);
+        if (two) row_body<NX, kSpecIn, kScreen, kSpecOut>(u1, ny, ra, d1, tw, smem, vb);
+    } else {
+        row_body<NX, kSpecIn, kScreen, kNaturalOut>(u0, ny, ra, d0, tw, smem, va);
+        if (two) row_body<NX, kSpecIn, kScreen, kNaturalOut>(u1, ny, ra, d1, tw, smem, vb);
+    }
 }
 
 template <int NY>
-__device__ __forceinline__ void batch_col(const BatchJob& jb, int tile, float2* smem) {
-    Twiddles<NY, kR> tw;
-    tw.load((const float2*)jb.twy, threadIdx.x / units_per_block<NY>());
-    col_unit<NY, false>(tile, jb.nx, (float2*)jb.work, (const float2*)jb.H, tw, smem, nullptr,
-                        nullptr, nullptr);
+__device__ __attribute__((noinline)) void batch_col(g_float2* work_g, const g_float2* H_g,
+                                                    const g_float2* twy, int nx, int item,
+                                                    lds_float2* lds) {
+    float2* smem = (float2*)lds;
+    float2* work = (float2*)work_g;
+    const float2* H = (const float2*)H_g;
+    OpaqueTwiddles<NY, kR> tw;
+    tw.load((const float2*)twy, threadIdx.x / units_per_block<NY>());
+    const int units = (nx + units_per_block<NY>() - 1) / units_per_block<NY>();
+    const int u0 = item * kUnitsPerItem, u1 = u0 + 1;
+    const bool two = u1 < units;
+    float2 va[kR], ha[kR], vb[kR], hb[kR];
+    col_load<NY>(u0, nx, work, H, va, ha);
+    if (two) col_load<NY>(u1, nx, work, H, vb, hb);
+    col_body<NY, false>(u0, nx, work, tw, smem, nullptr, nullptr, nullptr, va, ha);
+    if (two) col_body<NY, false>(u1, nx, work, tw, smem, nullptr, nullptr, nullptr, vb, hb);
 }
 
 __global__ __launch_bounds__(kBlock) void batch_kernel(const BatchJob* __restrict__ jobs,
                                                        const BatchSeg* __restrict__ segs,
                                                        int total, unsigned* q) {
     extern __shared__ float2 smem[];
+    lds_float2* lds = (lds_float2*)smem;
     __shared__ int s_item;
     int cursor = 0;
     bool abort = false;
@@ -95,24 +149,45 @@ __global__ __launch_bounds__(kBlock) void batch_kernel(const BatchJob* __restric
         __syncthreads();
         if (sg.pass % 2 == 0) {
             switch (jb.nx) {
-                case 32: batch_row<32>(jb, sg.pass, tile, smem); break;
-                case 64: batch_row<64>(jb, sg.pass, tile, smem); break;
-                case 128: batch_row<128>(jb, sg.pass, tile, smem); break;
-                case 256: batch_row<256>(jb, sg.pass, tile, smem); break;
-                case 512: batch_row<512>(jb, sg.pass, tile, smem); break;
-                case 1024: batch_row<1024>(jb, sg.pass, tile, smem); break;
-                case 2048: batch_row<2048>(jb, sg.pass, tile, smem); break;
+                case 32: batch_row<32>((const g_float2*)jb.field_in, (g_float2*)jb.work, (const g_float*)jb.dn,
+                                                  (g_float*)jb.inten, (const g_float2*)jb.twx, jb.nx,
+                                                  jb.ny, jb.steps, jb.k0dz, sg.pass, tile, lds); break;
+                case 64: batch_row<64>((const g_float2*)jb.field_in, (g_float2*)jb.work, (const g_float*)jb.dn,
+                                                  (g_float*)jb.inten, (const g_float2*)jb.twx, jb.nx,
+                                                  jb.ny, jb.steps, jb.k0dz, sg.pass, tile, lds); break;
+                case 128: batch_row<128>((const g_float2*)jb.field_in, (g_float2*)jb.work, (const g_float*)jb.dn,
+                                                  (g_float*)jb.inten, (const g_float2*)jb.twx, jb.nx,
+                                                  jb.ny, jb.steps, jb.k0dz, sg.pass, tile, lds); break;
+                case 256: batch_row<256>((const g_float2*)jb.field_in, (g_float2*)jb.work, (const g_float*)jb.dn,
+                                                  (g_float*)jb.inten, (const g_float2*)jb.twx, jb.nx,
+                                                  jb.ny, jb.steps, jb.k0dz, sg.pass, tile, lds); break;
+                case 512: batch_row<512>((const g_float2*)jb.field_in, (g_float2*)jb.work, (const g_float*)jb.dn,
+                                                  (g_float*)jb.inten, (const g_float2*)jb.twx, jb.nx,
+                                                  jb.ny, jb.steps, jb.k0dz, sg.pass, tile, lds); break;
+                case 1024: batch_row<1024>((const g_float2*)jb.field_in, (g_float2*)jb.work, (const g_float*)jb.dn,
+                                                  (g_float*)jb.inten, (const g_float2*)jb.twx, jb.nx,
+                                                  jb.ny, jb.steps, jb.k0dz, sg.pass, tile, lds); break;
+                case 2048: batch_row<2048>((const g_float2*)jb.field_in, (g_float2*)jb.work, (const g_float*)jb.dn,
+                                                  (g_float*)jb.inten, (const g_float2*)jb.twx, jb.nx,
+                                                  jb.ny, jb.steps, jb.k0dz, sg.pass, tile, lds); break;
                 default: break;
             }
         } else {
             switch (jb.ny) {
-                case 32: batch_col<32>(jb, tile, smem); break;
-                case 64: batch_col<64>(jb, tile, smem); break;
-                case 128: batch_col<128>(jb, tile, smem); break;
-                case 256: batch_col<256>(jb, tile, smem); break;
-                case 512: batch_col<512>(jb, tile, smem); break;
-                case 1024: batch_col<1024>(jb, tile, smem); break;
-                case 2048: batch_col<2048>(jb, tile, smem); break;
+                case 32: batch_col<32>((g_float2*)jb.work, (const g_float2*)jb.H,
+                                                  (const g_float2*)jb.twy, jb.nx, tile, lds); break;
+                case 64: batch_col<64>((g_float2*)jb.work, (const g_float2*)jb.H,
+                                                  (const g_float2*)jb.twy, jb.nx, tile, lds); break;
+                case 128: batch_col<128>((g_float2*)jb.work, (const g_float2*)jb.H,
+                                                  (const g_float2*)jb.twy, jb.nx, tile, lds); break;
+                case 256: batch_col<256>((g_float2*)jb.work, (const g_float2*)jb.H,
+                                                  (const g_float2*)jb.twy, jb.nx, tile, lds); break;
+                case 512: batch_col<512>((g_float2*)jb.work, (const g_float2*)jb.H,
+                                                  (const g_float2*)jb.twy, jb.nx, tile, lds); break;
+                case 1024: batch_col<1024>((g_float2*)jb.work, (const g_float2*)jb.H,
+                                                  (const g_float2*)jb.twy, jb.nx, tile, lds); break;
+                case 2048: batch_col<2048>((g_float2*)jb.work, (const g_float2*)jb.H,
+                                                  (const g_float2*)jb.twy, jb.nx, tile, lds); break;
                 default: break;
             }
         }
@@ -160,5 +235,7 @@ int col_units(int nx, int ny) {
     const int w = kBlock / (ny / kR);
     return (nx + w - 1) / w;
 }
+int row_items(int nx, int ny) { return (row_units(nx, ny) + kUnitsPerItem - 1) / kUnitsPerItem; }
+int col_items(int nx, int ny) { return (col_units(nx, ny) + kUnitsPerItem - 1) / kUnitsPerItem; }
 
 }  // namespace bpm

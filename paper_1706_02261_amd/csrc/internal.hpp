@@ -83,8 +83,11 @@ struct BatchSeg {
     int job, pass, first, count, need;
 };
 int batch_queue_words(int n_jobs);
+constexpr int kUnitsPerItem = 2;  // units of one pass per work item
 int row_units(int nx, int ny);
 int col_units(int nx, int ny);
+int row_items(int nx, int ny);  // work items of one row pass
+int col_items(int nx, int ny);  // work items of one column pass
 hipError_t launch_batch(const BatchJob* jobs_dev, const BatchSeg* segs_dev, int total,
                         unsigned* q, int n_jobs, hipStream_t s);
 
