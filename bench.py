@@ -22,7 +22,7 @@ Prints ONE JSON line:
              (the first slices of the same volume), with the relative L2
              error of the GPU field against it on that sample
 
-`--gpus N` with N > 1 exits: this build runs on one GPU.
+`--gpus N` with N > 1 exits: the benchmark runs on one GPU.
 """
 from __future__ import annotations
 
@@ -99,21 +99,54 @@ SURROGATE_FLOP_PER_PSF = 2 * (8192 * 32 * 216 + 4096 * 32 * 864 + 2048 * 32 * 86
 MFMA_BF16_PEAK_TFLOPS = 2500.0
 
 
-def psf_rates(dev, n_runs=8, n_infer=16384):
-    """PSFs/s of the BPM (multiplexed march + readout, 1024 sources per run at
-    depths spread over the 64-slice volume) and of the surrogate (patch
-    extraction + inference, error head included) on the same volume; the
-    surrogate's rate does not depend on its weights, so an untrained network
-    is timed."""
+def psf_rates(dev, n_runs=8, n_infer=100000, train_seconds=30.0):
+    """The learned PSF surrogate against the BPM on the same GPU.
+
+    * BPM PSFs/s: multiplexed runs (1024 sources each, depths spread over the
+      64-slice volume; point sources + march + readout);
+    * the surrogate is trained for `train_seconds` on BPM PSFs of two volumes
+      (16 runs, 16384 PSFs) and evaluated on 2048 held-out PSFs of a third:
+      relative L2 error against the BPM, the error of the spatially invariant
+      clear-medium PSF, the fraction above the 5 % fallback threshold;
+    * surrogate PSFs/s on `n_infer` random sources of a fourth volume (patch
+      extraction + network + error head), and the effective rate of the whole
+      path with the BPM fallback for every source predicted above 5 %."""
     import numpy as np
     import torch
     import synth
     from paper_1706_02261_amd import psfs
     from paper_1706_02261_amd import surrogate as S
-    vol = torch.from_numpy(synth.surrogate_volume(3)).to(dev)
-    scale = 1.0 / psfs.reference_peak(1024, 1024, device=dev)
-    depths = [int(d) for d in np.linspace(2, 62, n_runs)]
     stream = torch.cuda.current_stream(dev)
+    ev = lambda: torch.cuda.Event(enable_timing=True)
+    scale = 1.0 / psfs.reference_peak(1024, 1024, device=dev)
+    gen = np.random.default_rng(45)
+
+    def runs(vol, n):
+        out = [psfs.training_run(vol, int(gen.integers(0, 64)),
+                                 (int(gen.integers(0, 32)), int(gen.integers(0, 32))), 32, scale)
+               for _ in range(n)]
+        return [torch.cat([o[k] for o in out]) for k in range(3)]
+
+    train = [runs(torch.from_numpy(synth.surrogate_volume(c)).to(dev), 8) for c in (0, 1)]
+    X, D, T = (torch.cat([t[k] for t in train]) for k in range(3))
+    del train
+    Xv, Dv, Tv = runs(torch.from_numpy(synth.surrogate_volume(2)).to(dev), 2)
+    model = S.PSFSurrogate(dev, S.init_params(seed=0))
+    epochs = model.fit(X, D, T, seconds=train_seconds)
+    del X, D, T
+    blob = model.export()
+    pred, err = S.infer(blob, Xv, Dv)
+    rel = lambda a, b: (a - b).flatten(1).norm(dim=1) / b.flatten(1).norm(dim=1)
+    r_s = rel(pred, Tv)
+    clear = psfs.bpm_psfs(torch.zeros((64, 1024, 1024), device=dev), 32,
+                          torch.tensor([[512, 512]], dtype=torch.int32, device=dev), scale)
+    r_inv = rel(clear.expand_as(Tv), Tv)
+    q = lambda v, p: round(float(torch.quantile(v.float().cpu(), p)), 4)
+    corr = float(np.corrcoef(err.cpu().numpy(), r_s.cpu().numpy())[0, 1])
+    del Xv, Dv, Tv, pred
+
+    vol = torch.from_numpy(synth.surrogate_volume(3)).to(dev)
+    depths = [int(d) for d in np.linspace(2, 62, n_runs)]
 
     def bpm_all():
         n = 0
@@ -123,43 +156,45 @@ def psf_rates(dev, n_runs=8, n_infer=16384):
         return n
 
     bpm_all()
-    a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    a, b = ev(), ev()
     torch.cuda.synchronize(dev)
     a.record(stream)
     n_bpm = bpm_all()
     b.record(stream)
     torch.cuda.synchronize(dev)
     t_bpm = a.elapsed_time(b) / 1e3
-    gen = np.random.default_rng(5)
-    src = torch.from_numpy(np.stack([gen.integers(0, 1024, n_infer),
+    src = torch.from_numpy(np.stack([gen.integers(0, 64, n_infer), gen.integers(0, 1024, n_infer),
                                      gen.integers(0, 1024, n_infer)], 1).astype(np.int32)).to(dev)
-    depth = torch.from_numpy(gen.integers(0, 64, n_infer).astype(np.float32)).to(dev)
-    blob = S.PSFSurrogate(dev, S.init_params(seed=1)).export()
-    out = torch.empty((n_infer,) + S.PSF, device=dev)
-    err = torch.empty(n_infer, device=dev)
-    patches = torch.empty((n_infer,) + S.PATCH, device=dev)
-    ws = S.workspace(max(int(S.lib().psf_surrogate_workspace_size(n_infer, 0)), 256), dev)
 
-    def infer():
-        S.extract_patches(vol, src, 0, out=patches)
-        S.infer(blob, patches, depth, psf_out=out, pred_err=err, ws=ws)
+    def timed(threshold):
+        a, b = ev(), ev()
+        torch.cuda.synchronize(dev)
+        a.record(stream)
+        _, e, fb = psfs.psf_with_fallback(blob, vol, src, scale, threshold=threshold)
+        b.record(stream)
+        torch.cuda.synchronize(dev)
+        return a.elapsed_time(b) / 1e3, float(fb.float().mean())
 
-    infer()
-    torch.cuda.synchronize(dev)
-    a.record(stream)
-    infer()
-    b.record(stream)
-    torch.cuda.synchronize(dev)
-    t_s = a.elapsed_time(b) / 1e3
+    timed(float("inf"))
+    t_s, _ = timed(float("inf"))
+    t_eff, fb_rate = timed(0.05)
     tflops = SURROGATE_FLOP_PER_PSF * n_infer / t_s / 1e12
     return {
         "bpm_psfs_per_s": round(n_bpm / t_bpm, 1),
         "bpm_sample": f"{n_runs} multiplexed runs of 1024 sources, 1024^2 x (64 - d) slices, "
                       f"d in {depths[0]}..{depths[-1]}, 32-plane readout, 32^3 crops",
         "surrogate_psfs_per_s": round(n_infer / t_s, 1),
-        "surrogate_sample": f"{n_infer} sources, patch extraction + BF16 inference with "
-                            "error head",
+        "surrogate_sample": f"{n_infer} random sources (depth, y, x) of a 64 x 1024^2 volume: "
+                            "patch extraction + BF16 inference with error head",
         "surrogate_vs_bpm": round((n_infer / t_s) / (n_bpm / t_bpm), 4),
+        "effective_psfs_per_s": round(n_infer / t_eff, 1),
+        "fallback_rate": round(fb_rate, 4),
+        "training": {"psfs": 16384, "seconds": train_seconds, "epochs": epochs},
+        "heldout": {"psfs": 2048, "rel_err_median": q(r_s, 0.5), "rel_err_p95": q(r_s, 0.95),
+                    "invariant_psf_rel_err_median": q(r_inv, 0.5),
+                    "invariant_psf_rel_err_p95": q(r_inv, 0.95),
+                    "error_head_corr": round(corr, 3),
+                    "above_5pct": round(float((err > 0.05).float().mean()), 4)},
         "surrogate_roofline": {"bound": "mfma", "achieved": round(tflops, 2),
                                "peak": MFMA_BF16_PEAK_TFLOPS, "unit": "TFLOP/s",
                                "frac": round(tflops / MFMA_BF16_PEAK_TFLOPS, 5),
@@ -279,7 +314,7 @@ def main():
     args = ap.parse_args()
     world = int(os.environ.get("WORLD_SIZE", "1"))
     if args.gpus != 1 or world != 1:
-        print(f"bench.py: this build runs on one GPU; --gpus {args.gpus} (WORLD_SIZE "
+        print(f"bench.py: the benchmark runs on one GPU; --gpus {args.gpus} (WORLD_SIZE "
               f"{world}) is not supported", file=sys.stderr)
         sys.exit(2)
 

@@ -1,7 +1,7 @@
 /*
  * FP64 CPU oracle of the PSF surrogate's convolution layers.
  *
- * TEST INFRASTRUCTURE ONLY (see oracle.c).  The surrogate is this build's
+ * TEST INFRASTRUCTURE ONLY (see oracle.c).  The surrogate is this library's
  * own learned component (the paper has none); its layers are plain 3-D
  * cross-correlations with zero padding and strides, evaluated here by direct
  * loops in double precision on whatever (for instance bf16-rounded) operands

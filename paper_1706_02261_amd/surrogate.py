@@ -244,6 +244,38 @@ class PSFSurrogate:
             self.step_count += 1
         return self.loss
 
+    def fit(self, dn_patches, depth, target, seconds: float | None = None,
+            epochs: int | None = None, batch: int = 64, lr: float = 1e-3,
+            err_weight: float = 1.0, seed: int = 0, log=None) -> int:
+        """Adam over shuffled mini-batches until ``epochs`` epochs or ``seconds``
+        of wall time have passed (whichever is given; both: the first reached).
+        The learning rate rises linearly over the first epoch and then decays as
+        lr / (1 + 0.05 (epoch - 1)).  Returns the number of epochs run."""
+        import time
+        if seconds is None and epochs is None:
+            raise ValueError("give seconds or epochs")
+        n = dn_patches.shape[0]
+        nb = n // batch
+        if nb < 1:
+            raise ValueError(f"{n} samples are fewer than one batch of {batch}")
+        order = torch.Generator().manual_seed(seed)
+        t0 = time.perf_counter()
+        epoch = 0
+        while ((epochs is None or epoch < epochs) and
+               (seconds is None or time.perf_counter() - t0 < seconds)):
+            perm = torch.randperm(n, generator=order).to(self.device)
+            total = torch.zeros(2, dtype=torch.float32, device=self.device)
+            for b in range(nb):
+                i = perm[b * batch:(b + 1) * batch]
+                rate = lr * min(1.0, (epoch * nb + b + 1) / nb) / (1.0 + 0.05 * max(0, epoch - 1))
+                total += self.train_step(dn_patches[i].contiguous(), depth[i].contiguous(),
+                                         target[i].contiguous(), lr=rate, err_weight=err_weight)
+            torch.cuda.synchronize(self.device)
+            epoch += 1
+            if log is not None:
+                log(epoch, (total / nb).tolist(), time.perf_counter() - t0)
+        return epoch
+
     def gradients(self, stream=None) -> torch.Tensor:
         g = torch.empty(param_count(), dtype=torch.float32, device=self.device)
         check(lib().psf_surrogate_gradients(_ptr(self.state), _ptr(g), _stream_ptr(stream)),

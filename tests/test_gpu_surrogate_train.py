@@ -16,8 +16,6 @@ network beats the invariant PSF and that fallback stacks are bitwise the BPM
 readout.  Accuracy within 5 % for every source is a statistical target, not
 asserted (parity unpinned).
 """
-import time
-
 import numpy as np
 import pytest
 
@@ -65,24 +63,9 @@ def trained():
     Dtr = torch.cat([data[0][2], data[1][2]])
     Ttr = torch.cat([data[0][3], data[1][3]])
     model = S.PSFSurrogate("cuda", S.init_params(seed=0))
-    order = torch.Generator(device="cpu").manual_seed(0)
-    t0 = time.perf_counter()
-    epoch = 0
-    while time.perf_counter() - t0 < TRAIN_SECONDS:
-        perm = torch.randperm(Xtr.shape[0], generator=order).cuda()
-        total = torch.zeros(2, device="cuda")
-        nb = Xtr.shape[0] // BATCH
-        for b in range(nb):
-            i = perm[b * BATCH:(b + 1) * BATCH]
-            step = epoch * nb + b
-            # linear warm-up over the first epoch, then a slow decay
-            lr = LR * min(1.0, (step + 1) / nb) / (1.0 + 0.05 * max(0, epoch - 1))
-            total += model.train_step(Xtr[i].contiguous(), Dtr[i].contiguous(),
-                                      Ttr[i].contiguous(), lr=lr, err_weight=1.0)
-        torch.cuda.synchronize()
-        epoch += 1
-        print(f"epoch {epoch}: loss {(total / nb).tolist()} "
-              f"({time.perf_counter() - t0:.1f} s)", flush=True)
+    epoch = model.fit(Xtr, Dtr, Ttr, seconds=TRAIN_SECONDS, batch=BATCH, lr=LR, err_weight=1.0,
+                      log=lambda e, loss, t: print(f"epoch {e}: loss {loss} ({t:.1f} s)",
+                                                   flush=True))
     return {"model": model, "blob": model.export(), "val": data[2], "scale": scale,
             "epochs": epoch}
 
