@@ -243,9 +243,13 @@ __global__ __launch_bounds__(256) void conv_bwd_data_kernel(const u16* __restric
 }
 
 // ---------------------------------------------------------------------------
-// convolution backward, weights: dw[co][k] += sum over positions dy[pos][co] x[pos, k]
-// Each wave reduces a contiguous chunk of output positions for a 32 (co) x
-// 32 (k) tile; the four waves of a block add their tiles in LDS, then one
+// convolution backward, weights: dw[co][k] += sum over positions of dy[pos][co] x[pos, k]
+// The reduction runs over output positions, which are the slow index of the
+// channels-last tensors, so each wave stages 16 positions x 32 channels of dy
+// and of the gathered input (16-byte loads, one per lane and operand) in LDS
+// and reads them back transposed (8 positions of one channel per lane) for
+// the MFMA.  Each wave reduces a contiguous chunk of positions for a 32 (co)
+// x 32 (k) tile; the four waves of a block add their tiles in LDS, then one
 // atomic add per element into the fp32 gradient.
 
 __global__ __launch_bounds__(256) void conv_bwd_weight_kernel(const u16* __restrict__ x,
@@ -254,79 +258,104 @@ __global__ __launch_bounds__(256) void conv_bwd_weight_kernel(const u16* __restr
                                                               const int4* __restrict__ taps,
                                                               int chunk, float* __restrict__ dw) {
     __shared__ float red[4][32][33];
+    __shared__ u16 stage[4][2][16 * 32];
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6, half = lane >> 5;
     const long P = (long)c.N * c.Do * c.Ho * c.Wo;
     const int k0 = blockIdx.x * 32, co0 = blockIdx.y * 32;
-    const int kidx = k0 + (lane & 31);
-    const bool kon = kidx < c.K;
-    const int4 t = taps[(kon ? kidx : 0) / 8];
-    const int ci = t.w + (kidx & 7);
-    const int co = co0 + (lane & 31);
+    // this lane's loads: position pp of the 16, channel chunk c4 of the 4
+    const int pp = lane >> 2, c4 = lane & 3;
+    const int kc = k0 / 8 + c4;  // 8-wide chunk of the reduction index
+    const bool kon = 8 * kc < c.K;
+    const int4 t = taps[kon ? kc : 0];
+    u16* sd = stage[wave][0];
+    u16* sx = stage[wave][1];
     const long pbeg = ((long)blockIdx.z * 4 + wave) * chunk;
     const long pend = pbeg + chunk < P ? pbeg + chunk : P;
     f32x16 acc = {};
     for (long p0 = pbeg; p0 < pend; p0 += 16) {
+        const long p = p0 + pp;
+        uint4 dv = make_uint4(0, 0, 0, 0), xv = make_uint4(0, 0, 0, 0);
+        if (p < pend) {
+            dv = *reinterpret_cast<const uint4*>(dy + (size_t)p * c.Co + co0 + c4 * 8);
+            if (kon) {
+                long q = p;
+                const int ox = (int)(q % c.Wo);
+                q /= c.Wo;
+                const int oy = (int)(q % c.Ho);
+                q /= c.Ho;
+                const int oz = (int)(q % c.Do);
+                const int n = (int)(q / c.Do);
+                const int iz = oz * c.sd - c.pd + t.x, iy = oy * c.sh - c.ph + t.y,
+                          ix = ox * c.sw - c.pw + t.z;
+                if ((unsigned)iz < (unsigned)c.D && (unsigned)iy < (unsigned)c.H &&
+                    (unsigned)ix < (unsigned)c.W)
+                    xv = *reinterpret_cast<const uint4*>(
+                        x + ((((size_t)n * c.D + iz) * c.H + iy) * c.W + ix) * c.Ci + t.w);
+            }
+        }
+        *reinterpret_cast<uint4*>(sd + pp * 32 + c4 * 8) = dv;
+        *reinterpret_cast<uint4*>(sx + pp * 32 + c4 * 8) = xv;
+        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+        __builtin_amdgcn_wave_barrier();
+        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+        // lane: channel (co or k) lane % 32, positions 8 half .. 8 half + 7
         unsigned short av[8], bv[8];
 #pragma unroll
         for (int j = 0; j < 8; ++j) {
-            const long p = p0 + half * 8 + j;
-            av[j] = 0;
-            bv[j] = 0;
-            if (p < pend) {
-                av[j] = dy[(size_t)p * c.Co + co];
-                if (kon) {
-                    long q = p;
-                    const int ox = (int)(q % c.Wo);
-                    q /= c.Wo;
-                    const int oy = (int)(q % c.Ho);
-                    q /= c.Ho;
-                    const int oz = (int)(q % c.Do);
-                    const int n = (int)(q / c.Do);
-                    const int iz = oz * c.sd - c.pd + t.x, iy = oy * c.sh - c.ph + t.y,
-                              ix = ox * c.sw - c.pw + t.z;
-                    if ((unsigned)iz < (unsigned)c.D && (unsigned)iy < (unsigned)c.H &&
-                        (unsigned)ix < (unsigned)c.W)
-                        bv[j] = x[((((size_t)n * c.D + iz) * c.H + iy) * c.W + ix) * c.Ci + ci];
-                }
-            }
+            av[j] = sd[(8 * half + j) * 32 + (lane & 31)];
+            bv[j] = sx[(8 * half + j) * 32 + (lane & 31)];
         }
-        uint4 a, b;
-        a.x = av[0] | ((unsigned)av[1] << 16);
-        a.y = av[2] | ((unsigned)av[3] << 16);
-        a.z = av[4] | ((unsigned)av[5] << 16);
-        a.w = av[6] | ((unsigned)av[7] << 16);
-        b.x = bv[0] | ((unsigned)bv[1] << 16);
-        b.y = bv[2] | ((unsigned)bv[3] << 16);
-        b.z = bv[4] | ((unsigned)bv[5] << 16);
-        b.w = bv[6] | ((unsigned)bv[7] << 16);
-        acc = mfma(a, b, acc);
+        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+        __builtin_amdgcn_wave_barrier();
+        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+        uint4 av4, bv4;
+        av4.x = av[0] | ((unsigned)av[1] << 16);
+        av4.y = av[2] | ((unsigned)av[3] << 16);
+        av4.z = av[4] | ((unsigned)av[5] << 16);
+        av4.w = av[6] | ((unsigned)av[7] << 16);
+        bv4.x = bv[0] | ((unsigned)bv[1] << 16);
+        bv4.y = bv[2] | ((unsigned)bv[3] << 16);
+        bv4.z = bv[4] | ((unsigned)bv[5] << 16);
+        bv4.w = bv[6] | ((unsigned)bv[7] << 16);
+        acc = mfma(av4, bv4, acc);
     }
 #pragma unroll
     for (int i = 0; i < 16; ++i) red[wave][8 * (i / 4) + 4 * half + i % 4][lane & 31] = acc[i];
     __syncthreads();
     for (int e = threadIdx.x; e < 32 * 32; e += 256) {
         const int r = e / 32, col = e % 32;
-        const float s = red[0][r][col] + red[1][r][col] + red[2][r][col] + red[3][r][col];
-        if (k0 + col < c.K && s != 0.f)
-            atomicAdd(dw + (size_t)(co0 + r) * c.Kp + k0 + col, s);
+        const float v = red[0][r][col] + red[1][r][col] + red[2][r][col] + red[3][r][col];
+        if (k0 + col < c.K && v != 0.f)
+            atomicAdd(dw + (size_t)(co0 + r) * c.Kp + k0 + col, v);
     }
 }
 
-// bias gradient: db[co] += sum over positions of dy[pos][co]; blockDim.x = 256,
-// Co divides 256
+// bias gradient: db[co] += sum over positions of dy[pos][co].  blockDim.x = 256;
+// a thread adds 8 channels (one 16-byte load) of every G-th position, G =
+// 256 / (Co / 8); the block then adds its G partial sums per channel.
 __global__ void bias_grad_kernel(const u16* __restrict__ dy, long P, int Co,
                                  float* __restrict__ db) {
-    __shared__ float part[256];
-    const int co = threadIdx.x % Co, lanes = blockDim.x / Co;
-    float s = 0.f;
-    for (long p = (long)blockIdx.x * lanes + threadIdx.x / Co; p < P; p += (long)gridDim.x * lanes)
-        s += bf2f(dy[(size_t)p * Co + co]);
-    part[threadIdx.x] = s;
+    __shared__ float part[256 * 8];
+    const int cch = Co / 8, c8 = threadIdx.x % cch, grp = threadIdx.x / cch;
+    const int G = blockDim.x / cch;
+    float s[8] = {};
+    for (long p = (long)blockIdx.x * G + grp; p < P; p += (long)gridDim.x * G) {
+        const uint4 v = *reinterpret_cast<const uint4*>(dy + (size_t)p * Co + c8 * 8);
+        const unsigned w[4] = {v.x, v.y, v.z, v.w};
+#pragma unroll
+        for (int i = 0; i < 4; ++i) {
+            s[2 * i] += bf2f((u16)(w[i] & 0xffffu));
+            s[2 * i + 1] += bf2f((u16)(w[i] >> 16));
+        }
+    }
+#pragma unroll
+    for (int i = 0; i < 8; ++i) part[threadIdx.x * 8 + i] = s[i];
     __syncthreads();
     if (threadIdx.x < Co) {
+        const int ch = threadIdx.x, cc = ch / 8, i = ch % 8;
         float t = 0.f;
-        for (int j = threadIdx.x; j < (int)blockDim.x; j += Co) t += part[j];
-        atomicAdd(db + co, t);
+        for (int g = 0; g < G; ++g) t += part[(g * cch + cc) * 8 + i];
+        atomicAdd(db + ch, t);
     }
 }
 
@@ -636,7 +665,10 @@ hipError_t conv_backward_weight(const ConvGeo& c, const void* x, const void* dy,
     }
     hipError_t e = hipGetLastError();
     if (e != hipSuccess || !db) return e;
-    bias_grad_kernel<<<grid_for(P / 8 + 1), 256, 0, s>>>((const u16*)dy, P, c.Co, db);
+    const long per_block = 256L / (c.Co / 8) * 64;  // positions per block, 64 rounds
+    const long blocks = (P + per_block - 1) / per_block;
+    bias_grad_kernel<<<(unsigned)(blocks < 65535 ? blocks : 65535), 256, 0, s>>>(
+        (const u16*)dy, P, c.Co, db);
     return hipGetLastError();
 }
 

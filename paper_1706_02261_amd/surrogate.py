@@ -245,12 +245,17 @@ class PSFSurrogate:
         return self.loss
 
     def fit(self, dn_patches, depth, target, seconds: float | None = None,
-            epochs: int | None = None, batch: int = 64, lr: float = 1e-3,
-            err_weight: float = 1.0, seed: int = 0, log=None) -> int:
+            epochs: int | None = None, batch: int = 64, lr: float = 5e-4,
+            err_weight: float = 1.0, seed: int = 0, warmup_steps: int = 1000,
+            log=None) -> int:
         """Adam over shuffled mini-batches until ``epochs`` epochs or ``seconds``
         of wall time have passed (whichever is given; both: the first reached).
-        The learning rate rises linearly over the first epoch and then decays as
-        lr / (1 + 0.05 (epoch - 1)).  Returns the number of epochs run."""
+        The learning rate rises linearly over the first ``warmup_steps`` steps
+        and then decays as lr / (1 + 0.05 e), e = epochs since the warm-up.  A
+        short warm-up to a large rate drives the softplus output of the PSF
+        layer to zero everywhere within a few hundred steps (loss 1, vanishing
+        gradient), a state training leaves only after tens of epochs.  Returns
+        the number of epochs run."""
         import time
         if seconds is None and epochs is None:
             raise ValueError("give seconds or epochs")
@@ -261,15 +266,18 @@ class PSFSurrogate:
         order = torch.Generator().manual_seed(seed)
         t0 = time.perf_counter()
         epoch = 0
+        k = 0
+        warm = max(1, warmup_steps)
         while ((epochs is None or epoch < epochs) and
                (seconds is None or time.perf_counter() - t0 < seconds)):
             perm = torch.randperm(n, generator=order).to(self.device)
             total = torch.zeros(2, dtype=torch.float32, device=self.device)
             for b in range(nb):
                 i = perm[b * batch:(b + 1) * batch]
-                rate = lr * min(1.0, (epoch * nb + b + 1) / nb) / (1.0 + 0.05 * max(0, epoch - 1))
+                rate = lr * min(1.0, (k + 1) / warm) / (1.0 + 0.05 * max(0, k + 1 - warm) / nb)
                 total += self.train_step(dn_patches[i].contiguous(), depth[i].contiguous(),
                                          target[i].contiguous(), lr=rate, err_weight=err_weight)
+                k += 1
             torch.cuda.synchronize(self.device)
             epoch += 1
             if log is not None:

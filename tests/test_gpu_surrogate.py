@@ -212,13 +212,16 @@ def test_inference_matches_oracle_and_is_batch_invariant():
 
 
 def test_training_reduces_loss():
+    """200 Adam steps at 3e-4 on one batch of 16 at least halve the loss (at
+    this rate every seed tried leaves the initial plateau within 50 steps;
+    at 1e-3 some stay on it for a hundred)."""
     from paper_1706_02261_amd import surrogate as S
     model = S.PSFSurrogate("cuda", S.init_params(seed=8))
     dn, depth, target = batch(16, 9)
     dn_t, depth_t, tg_t = (torch.from_numpy(a).cuda() for a in (dn, depth, target))
     first = model.train_step(dn_t, depth_t, tg_t, lr=0.0).clone()
     for _ in range(200):
-        model.train_step(dn_t, depth_t, tg_t, lr=1e-3)
+        model.train_step(dn_t, depth_t, tg_t, lr=3e-4)
     last = model.train_step(dn_t, depth_t, tg_t, lr=0.0)
     torch.cuda.synchronize()
     assert model.step_count == 200

@@ -28,7 +28,7 @@ torch = pytest.importorskip("torch")
 RUNS_PER_VOLUME = 12
 TRAIN_SECONDS = 75.0
 BATCH = 64
-LR = 1e-3
+LR = 5e-4
 
 
 def runs(vol, n_runs, gen, scale):
