@@ -304,6 +304,8 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--slices", type=int, default=1024, help="march depth (default 1024)")
     ap.add_argument("--no-psf", action="store_true", help="skip the surrogate vs BPM PSF rates")
+    ap.add_argument("--train-seconds", type=float, default=30.0,
+                    help="surrogate training time of the PSF block (default 30)")
     ap.add_argument("--psf-only", action="store_true",
                     help="only the surrogate vs BPM PSF rates (for profiling those kernels)")
     ap.add_argument("--no-extra", action="store_true",
@@ -327,7 +329,8 @@ def main():
 
     dev = torch.device("cuda:0")
     if args.psf_only:
-        print(json.dumps({"metric": "surrogate vs BPM PSFs/s", "psf": psf_rates(dev)}), flush=True)
+        print(json.dumps({"metric": "surrogate vs BPM PSFs/s",
+                          "psf": psf_rates(dev, train_seconds=args.train_seconds)}), flush=True)
         return
     t_gen = time.perf_counter()
     g, u0, dn_host = synth.config2_detection(steps=args.slices)
@@ -423,7 +426,7 @@ def main():
         torch.cuda.synchronize(dev)
         line["copy_calibration_bytes"] = src.numel() * 4
     if not args.no_psf:
-        line["psf"] = psf_rates(dev)
+        line["psf"] = psf_rates(dev, train_seconds=args.train_seconds)
     if not args.no_extra:
         line["adjoint"] = adjoint_rate(dev)
         line["uneven_batch"] = batch_rate(dev)

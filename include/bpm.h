@@ -122,6 +122,30 @@ size_t bpm_batch_workspace_size(const bpm_job* jobs, int n_jobs);
 int bpm_propagate_batch(const bpm_job* jobs, int n_jobs,
                         void* workspace, size_t workspace_bytes, void* hip_stream);
 
+/* The uneven batch in two halves, so that the device half can be captured
+ * into a HIP graph (stream capture) and replayed.  Both always take the
+ * work-queue path (never the lockstep one) and produce, bit for bit, the
+ * results of bpm_propagate_batch; workspace size as for bpm_propagate_batch.
+ *
+ * bpm_batch_upload: builds the job and segment tables on the host and copies
+ *   them into `workspace` on `hip_stream` (through library-owned pinned
+ *   staging), together with a 64-bit key of the jobs and the workspace
+ *   address.  Must not be called while `hip_stream` is capturing
+ *   (BPM_ERR_INVALID_ARG).
+ * bpm_batch_launch: kernel launches and device-to-device copies only: the
+ *   per-job propagator tables, the copies of zero-step jobs, the queue reset
+ *   and the persistent batch kernel.  It reads the tables that
+ *   bpm_batch_upload left in `workspace` for the same `jobs` array contents;
+ *   if the workspace holds no tables or those of other jobs (the key differs)
+ *   the batch kernel returns at once and the outputs of jobs with steps > 0
+ *   are left untouched.  The caller must not modify the workspace between
+ *   upload and launch (or replays of a captured launch).
+ * Arguments are validated on the host as in bpm_propagate_batch. */
+int bpm_batch_upload(const bpm_job* jobs, int n_jobs,
+                     void* workspace, size_t workspace_bytes, void* hip_stream);
+int bpm_batch_launch(const bpm_job* jobs, int n_jobs,
+                     void* workspace, size_t workspace_bytes, void* hip_stream);
+
 /* Bytes of workspace for bpm_adjoint with an explicit checkpoint interval
  * (0 selects ceil(sqrt(steps))). */
 size_t bpm_adjoint_workspace_size(int nx, int ny, int steps, int checkpoint_every);

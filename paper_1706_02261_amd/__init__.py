@@ -5,9 +5,9 @@ runs in the library's HIP kernels; this package only checks and marshals
 torch tensors (device memory and streams) into the C ABI.
 """
 from ._lib import BpmError, lib  # noqa: F401
-from .bpm import (BPMFunction, PupilBPMFunction, adjoint, fft2, point_sources,  # noqa: F401
-                  propagate, propagate_batch, psf_readout,
+from .bpm import (BPMFunction, PreparedBatch, PupilBPMFunction, adjoint, fft2,  # noqa: F401
+                  point_sources, propagate, propagate_batch, psf_readout,
                   pupil_phase_grad, pupil_spectrum, workspace_size)
 
-__all__ = ["BpmError", "lib", "propagate", "propagate_batch", "adjoint", "fft2", "pupil_spectrum",
+__all__ = ["BpmError", "lib", "propagate", "propagate_batch", "PreparedBatch", "adjoint", "fft2", "pupil_spectrum",
            "pupil_phase_grad", "psf_readout", "point_sources", "BPMFunction", "PupilBPMFunction", "workspace_size"]

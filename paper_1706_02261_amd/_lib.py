@@ -24,7 +24,8 @@ BPM_WS_ADJOINT = 1
 # every symbol the headers under include/ declare
 EXPORTS = (
     "bpm_workspace_size", "bpm_propagate", "bpm_batch_workspace_size",
-    "bpm_propagate_batch", "bpm_adjoint_workspace_size", "bpm_adjoint",
+    "bpm_propagate_batch", "bpm_batch_upload", "bpm_batch_launch",
+    "bpm_adjoint_workspace_size", "bpm_adjoint",
     "psf_surrogate_infer", "bpm_error_string", "bpm_last_error",
     "bpm_fft2_workspace_size", "bpm_fft2", "bpm_pupil_spectrum", "bpm_pupil_phase_grad",
     "bpm_psf_readout_workspace_size", "bpm_psf_readout",
@@ -66,6 +67,9 @@ def _declare(L):
     L.bpm_batch_workspace_size.restype = _Z
     L.bpm_propagate_batch.argtypes = [ctypes.POINTER(Job), _I, _V, _Z, _V]
     L.bpm_propagate_batch.restype = _I
+    for name in ("bpm_batch_upload", "bpm_batch_launch"):
+        getattr(L, name).argtypes = [ctypes.POINTER(Job), _I, _V, _Z, _V]
+        getattr(L, name).restype = _I
     L.bpm_adjoint_workspace_size.argtypes = [_I, _I, _I, _I]
     L.bpm_adjoint_workspace_size.restype = _Z
     L.bpm_adjoint.argtypes = [_V, _V, _I, _I, _I, _D, _D, _D, _D, _V, _V, _V, _V, _V, _I,

@@ -215,14 +215,8 @@ class PupilBPMFunction(torch.autograd.Function):
         return gphi, None, gdn, None, None, None, None, None, None
 
 
-def propagate_batch(jobs, ws: torch.Tensor | None = None, stream=None):
-    """Run an uneven batch of marches in one persistent launch.
-
-    ``jobs``: sequence of dicts with keys field, dn, dx, dz, wavelength, n0 and
-    optional out, intensity (bool, default True), intensity_out.  Returns a
-    list of (field_out, intensity) per job."""
-    if len(jobs) == 0:
-        return []
+def _batch_table(jobs):
+    """ctypes job array and (out, intensity) tensors of a batch."""
     arr = (_lib.Job * len(jobs))()
     results = []
     dev = None
@@ -251,11 +245,44 @@ def propagate_batch(jobs, ws: torch.Tensor | None = None, stream=None):
     need = lib().bpm_batch_workspace_size(arr, len(jobs))
     if need == 0:
         raise _lib.BpmError(_lib.BPM_ERR_UNSUPPORTED_SIZE, "unsupported job in batch")
+    return arr, results, int(need), dev
+
+
+def propagate_batch(jobs, ws: torch.Tensor | None = None, stream=None):
+    """Run an uneven batch of marches in one persistent launch.
+
+    ``jobs``: sequence of dicts with keys field, dn, dx, dz, wavelength, n0 and
+    optional out, intensity (bool, default True), intensity_out.  Returns a
+    list of (field_out, intensity) per job."""
+    if len(jobs) == 0:
+        return []
+    arr, results, need, dev = _batch_table(jobs)
     if ws is None:
         ws = workspace(need, dev)
     rc = lib().bpm_propagate_batch(arr, len(jobs), _ptr(ws), ws.numel(), _stream_ptr(stream))
     check(rc, "bpm_propagate_batch")
     return results
+
+
+class PreparedBatch:
+    """An uneven batch whose tables sit in its own workspace, so that
+    ``launch()`` issues device work only and can be captured into a graph
+    (``torch.cuda.graph``) and replayed.  Inputs and outputs are the tensors
+    given (or allocated) here; a replay reads the inputs' current contents."""
+
+    def __init__(self, jobs, stream=None):
+        if len(jobs) == 0:
+            raise ValueError("a prepared batch needs at least one job")
+        self._jobs = list(jobs)  # keeps the input tensors alive
+        self._arr, self.results, need, dev = _batch_table(self._jobs)
+        self.ws = workspace(need, dev)
+        check(lib().bpm_batch_upload(self._arr, len(self._jobs), _ptr(self.ws), self.ws.numel(),
+                                     _stream_ptr(stream)), "bpm_batch_upload")
+
+    def launch(self, stream=None):
+        check(lib().bpm_batch_launch(self._arr, len(self._jobs), _ptr(self.ws), self.ws.numel(),
+                                     _stream_ptr(stream)), "bpm_batch_launch")
+        return self.results
 
 
 def psf_readout(exit_field: torch.Tensor, sources: torch.Tensor, dx: float, dz: float,

@@ -96,14 +96,47 @@ int bpm_propagate(const bpm_c64* field_in, const float* dn, int nx, int ny, int 
 namespace {
 
 // Host-side layout of a batch workspace: per-job plans, then the job table,
-// the segment table and the queue words.
+// the segment table, the queue words and the key of the uploaded tables.
 struct BatchLayout {
     std::vector<size_t> plan_off;
-    size_t jobs_off, segs_off, q_off, total;
+    size_t jobs_off, segs_off, q_off, key_off, total;
     int n_segs, n_items;
 };
 
 int batch_passes(const bpm_job& j) { return j.steps > 0 ? 2 * j.steps + 1 : 0; }
+
+// 64-bit FNV-1a over the fields of every job and the workspace address (the
+// plans' addresses are carved from it); never 0, so a zeroed workspace does
+// not match.  Written next to the tables at upload and passed to the batch
+// kernel at launch, which does nothing when the workspace holds the tables of
+// other jobs.
+unsigned long long batch_key(const bpm_job* jobs, int n, const void* ws) {
+    unsigned long long h = 1469598103934665603ull;
+    auto mix = [&h](const void* p, size_t bytes) {
+        const unsigned char* b = static_cast<const unsigned char*>(p);
+        for (size_t i = 0; i < bytes; ++i) {
+            h ^= b[i];
+            h *= 1099511628211ull;
+        }
+    };
+    mix(&n, sizeof n);
+    mix(&ws, sizeof ws);
+    for (int i = 0; i < n; ++i) {
+        const bpm_job& j = jobs[i];
+        mix(&j.field_in, sizeof j.field_in);
+        mix(&j.dn, sizeof j.dn);
+        mix(&j.field_out, sizeof j.field_out);
+        mix(&j.intensity_out, sizeof j.intensity_out);
+        mix(&j.nx, sizeof j.nx);
+        mix(&j.ny, sizeof j.ny);
+        mix(&j.steps, sizeof j.steps);
+        mix(&j.dx, sizeof j.dx);
+        mix(&j.dz, sizeof j.dz);
+        mix(&j.wavelength, sizeof j.wavelength);
+        mix(&j.n0, sizeof j.n0);
+    }
+    return h | 1ull;
+}
 
 BatchLayout batch_layout(const bpm_job* jobs, int n) {
     BatchLayout L;
@@ -127,6 +160,8 @@ BatchLayout batch_layout(const bpm_job* jobs, int n) {
     off += bpm::align_up(sizeof(bpm::BatchSeg) * (size_t)L.n_segs);
     L.q_off = off;
     off += bpm::align_up(sizeof(unsigned) * (size_t)bpm::batch_queue_words(n));
+    L.key_off = off;
+    off += bpm::align_up(sizeof(unsigned long long));
     L.total = off;
     return L;
 }
@@ -156,6 +191,104 @@ std::mutex g_stage_mu;
 void* g_stage = nullptr;
 size_t g_stage_bytes = 0;
 hipEvent_t g_stage_done = nullptr;
+
+// Host half of the work-queue batch: builds the job and segment tables and
+// uploads them into the workspace (stream-ordered, through pinned staging).
+int batch_tables(const bpm_job* jobs, int n_jobs, char* ws, const BatchLayout& L, hipStream_t s) {
+    int rc = BPM_OK;
+    // job table
+    std::vector<bpm::BatchJob> dj(n_jobs);
+    for (int i = 0; i < n_jobs; ++i) {
+        const bpm_job& j = jobs[i];
+        const bpm::Plan p = bpm::plan_carve(ws + L.plan_off[i], j.nx, j.ny);
+        dj[i] = bpm::BatchJob{j.field_in, j.dn, j.field_out, j.intensity_out, p.H, p.twx, p.twy,
+                              j.nx, j.ny, j.steps,
+                              (float)(2.0 * 3.14159265358979323846 / j.wavelength * j.dz)};
+    }
+    // segment table: round r holds pass r of every job that has it, jobs of
+    // equal pass size side by side
+    std::vector<int> order(n_jobs);
+    for (int i = 0; i < n_jobs; ++i) order[i] = i;
+    std::stable_sort(order.begin(), order.end(), [&](int a, int b) {
+        return jobs[a].nx != jobs[b].nx ? jobs[a].nx < jobs[b].nx : jobs[a].ny < jobs[b].ny;
+    });
+    int maxP = 0;
+    for (int i = 0; i < n_jobs; ++i) maxP = std::max(maxP, batch_passes(jobs[i]));
+    std::vector<bpm::BatchSeg> segs;
+    segs.reserve(L.n_segs);
+    int first = 0;
+    for (int r = 0; r < maxP; ++r) {
+        for (int i : order) {
+            if (r >= batch_passes(jobs[i])) continue;
+            const int R = bpm::row_items(jobs[i].nx, jobs[i].ny);
+            const int C = bpm::col_items(jobs[i].nx, jobs[i].ny);
+            const int count = (r % 2 == 0) ? R : C;
+            const int need = r == 0 ? 0 : R + (r / 2) * C + ((r - 1) / 2) * R;
+            segs.push_back(bpm::BatchSeg{i, r, first, count, need});
+            first += count;
+        }
+    }
+    // upload both tables through pinned staging
+    {
+        std::lock_guard<std::mutex> lk(g_stage_mu);
+        const size_t jb = sizeof(bpm::BatchJob) * dj.size();
+        const size_t sb = sizeof(bpm::BatchSeg) * segs.size();
+        const size_t kb_off = (jb + sb + 7) / 8 * 8;
+        const size_t bytes = kb_off + sizeof(unsigned long long);
+        const unsigned long long key = batch_key(jobs, n_jobs, ws);
+        hipError_t e = hipSuccess;
+        if (g_stage_done) e = hipEventSynchronize(g_stage_done);
+        if (e == hipSuccess && g_stage_bytes < bytes) {
+            if (g_stage) (void)hipHostFree(g_stage);
+            g_stage = nullptr;
+            g_stage_bytes = 0;
+            e = hipHostMalloc(&g_stage, bytes, hipHostMallocDefault);
+            if (e == hipSuccess) g_stage_bytes = bytes;
+        }
+        if (e == hipSuccess && !g_stage_done) e = hipEventCreateWithFlags(&g_stage_done, hipEventDisableTiming);
+        if (e == hipSuccess) {
+            std::memcpy(g_stage, dj.data(), jb);
+            std::memcpy(static_cast<char*>(g_stage) + jb, segs.data(), sb);
+            std::memcpy(static_cast<char*>(g_stage) + kb_off, &key, sizeof key);
+            e = hipMemcpyAsync(ws + L.jobs_off, g_stage, jb, hipMemcpyHostToDevice, s);
+        }
+        if (e == hipSuccess && sb)
+            e = hipMemcpyAsync(ws + L.segs_off, static_cast<char*>(g_stage) + jb, sb,
+                               hipMemcpyHostToDevice, s);
+        if (e == hipSuccess)
+            e = hipMemcpyAsync(ws + L.key_off, static_cast<char*>(g_stage) + kb_off, sizeof key,
+                               hipMemcpyHostToDevice, s);
+        if (e == hipSuccess) e = hipEventRecord(g_stage_done, s);
+        if ((rc = device_status(e, "batch tables"))) return rc;
+    }
+    return BPM_OK;
+}
+
+// Device half: plans, the copies of zero-step jobs, the queue reset and the
+// batch kernel.  Only kernel launches and device-to-device copies, so it can
+// be captured into a graph; it reads the tables batch_tables left in `ws`.
+int batch_device(const bpm_job* jobs, int n_jobs, char* ws, const BatchLayout& L, hipStream_t s) {
+    int rc = BPM_OK;
+    for (int i = 0; i < n_jobs; ++i) {
+        const bpm_job& j = jobs[i];
+        const bpm::Plan p = bpm::plan_carve(ws + L.plan_off[i], j.nx, j.ny);
+        if (j.steps > 0) {
+            const bpm::Geom g{j.nx, j.ny, j.steps, j.dx, j.dz, j.wavelength, j.n0};
+            if ((rc = device_status(bpm::launch_plan(g, p, true, s), "batch plan"))) return rc;
+        } else if ((const void*)j.field_out != (const void*)j.field_in) {
+            hipError_t e = hipMemcpyAsync(j.field_out, j.field_in,
+                                          sizeof(bpm_c64) * (size_t)j.nx * j.ny,
+                                          hipMemcpyDeviceToDevice, s);
+            if ((rc = device_status(e, "batch copy"))) return rc;
+        }
+    }
+    return device_status(bpm::launch_batch((const bpm::BatchJob*)(ws + L.jobs_off),
+                                           (const bpm::BatchSeg*)(ws + L.segs_off), L.n_items,
+                                           (unsigned*)(ws + L.q_off), n_jobs,
+                                           (const unsigned long long*)(ws + L.key_off),
+                                           batch_key(jobs, n_jobs, ws), s),
+                         "batch march");
+}
 
 }  // namespace
 
@@ -196,77 +329,32 @@ int bpm_propagate_batch(const bpm_job* jobs, int n_jobs, void* workspace,
         return device_status(bpm::launch_forward(g, p, io, n_jobs, s), "batch march");
     }
 
-    // job table, plans
-    std::vector<bpm::BatchJob> dj(n_jobs);
-    for (int i = 0; i < n_jobs; ++i) {
-        const bpm_job& j = jobs[i];
-        const bpm::Plan p = bpm::plan_carve(ws + L.plan_off[i], j.nx, j.ny);
-        dj[i] = bpm::BatchJob{j.field_in, j.dn, j.field_out, j.intensity_out, p.H, p.twx, p.twy,
-                              j.nx, j.ny, j.steps,
-                              (float)(2.0 * 3.14159265358979323846 / j.wavelength * j.dz)};
-        if (j.steps > 0) {
-            const bpm::Geom g{j.nx, j.ny, j.steps, j.dx, j.dz, j.wavelength, j.n0};
-            if ((rc = device_status(bpm::launch_plan(g, p, true, s), "batch plan"))) return rc;
-        } else if ((const void*)j.field_out != (const void*)j.field_in) {
-            hipError_t e = hipMemcpyAsync(j.field_out, j.field_in,
-                                          sizeof(bpm_c64) * (size_t)j.nx * j.ny,
-                                          hipMemcpyDeviceToDevice, s);
-            if ((rc = device_status(e, "batch copy"))) return rc;
-        }
-    }
-    // segment table: round r holds pass r of every job that has it, jobs of
-    // equal pass size side by side
-    std::vector<int> order(n_jobs);
-    for (int i = 0; i < n_jobs; ++i) order[i] = i;
-    std::stable_sort(order.begin(), order.end(), [&](int a, int b) {
-        return jobs[a].nx != jobs[b].nx ? jobs[a].nx < jobs[b].nx : jobs[a].ny < jobs[b].ny;
-    });
-    int maxP = 0;
-    for (int i = 0; i < n_jobs; ++i) maxP = std::max(maxP, batch_passes(jobs[i]));
-    std::vector<bpm::BatchSeg> segs;
-    segs.reserve(L.n_segs);
-    int first = 0;
-    for (int r = 0; r < maxP; ++r) {
-        for (int i : order) {
-            if (r >= batch_passes(jobs[i])) continue;
-            const int R = bpm::row_items(jobs[i].nx, jobs[i].ny);
-            const int C = bpm::col_items(jobs[i].nx, jobs[i].ny);
-            const int count = (r % 2 == 0) ? R : C;
-            const int need = r == 0 ? 0 : R + (r / 2) * C + ((r - 1) / 2) * R;
-            segs.push_back(bpm::BatchSeg{i, r, first, count, need});
-            first += count;
-        }
-    }
-    // upload both tables through pinned staging
-    {
-        std::lock_guard<std::mutex> lk(g_stage_mu);
-        const size_t jb = sizeof(bpm::BatchJob) * dj.size();
-        const size_t sb = sizeof(bpm::BatchSeg) * segs.size();
-        hipError_t e = hipSuccess;
-        if (g_stage_done) e = hipEventSynchronize(g_stage_done);
-        if (e == hipSuccess && g_stage_bytes < jb + sb) {
-            if (g_stage) (void)hipHostFree(g_stage);
-            g_stage = nullptr;
-            g_stage_bytes = 0;
-            e = hipHostMalloc(&g_stage, jb + sb, hipHostMallocDefault);
-            if (e == hipSuccess) g_stage_bytes = jb + sb;
-        }
-        if (e == hipSuccess && !g_stage_done) e = hipEventCreateWithFlags(&g_stage_done, hipEventDisableTiming);
-        if (e == hipSuccess) {
-            std::memcpy(g_stage, dj.data(), jb);
-            std::memcpy(static_cast<char*>(g_stage) + jb, segs.data(), sb);
-            e = hipMemcpyAsync(ws + L.jobs_off, g_stage, jb, hipMemcpyHostToDevice, s);
-        }
-        if (e == hipSuccess && sb)
-            e = hipMemcpyAsync(ws + L.segs_off, static_cast<char*>(g_stage) + jb, sb,
-                               hipMemcpyHostToDevice, s);
-        if (e == hipSuccess) e = hipEventRecord(g_stage_done, s);
-        if ((rc = device_status(e, "batch tables"))) return rc;
-    }
-    return device_status(bpm::launch_batch((const bpm::BatchJob*)(ws + L.jobs_off),
-                                           (const bpm::BatchSeg*)(ws + L.segs_off), first,
-                                           (unsigned*)(ws + L.q_off), n_jobs, s),
-                         "batch march");
+    if ((rc = batch_tables(jobs, n_jobs, ws, L, s))) return rc;
+    return batch_device(jobs, n_jobs, ws, L, s);
+}
+
+int bpm_batch_upload(const bpm_job* jobs, int n_jobs, void* workspace, size_t workspace_bytes,
+                     void* hip_stream) {
+    int rc = check_batch(jobs, n_jobs);
+    if (rc) return rc;
+    const BatchLayout L = batch_layout(jobs, n_jobs);
+    if ((rc = check_workspace(workspace, workspace_bytes, L.total))) return rc;
+    hipStream_t s = static_cast<hipStream_t>(hip_stream);
+    hipStreamCaptureStatus cs = hipStreamCaptureStatusNone;
+    if ((rc = device_status(hipStreamIsCapturing(s, &cs), "batch upload"))) return rc;
+    if (cs != hipStreamCaptureStatusNone)
+        return fail(BPM_ERR_INVALID_ARG, "bpm_batch_upload must not run under stream capture");
+    return batch_tables(jobs, n_jobs, static_cast<char*>(workspace), L, s);
+}
+
+int bpm_batch_launch(const bpm_job* jobs, int n_jobs, void* workspace, size_t workspace_bytes,
+                     void* hip_stream) {
+    int rc = check_batch(jobs, n_jobs);
+    if (rc) return rc;
+    const BatchLayout L = batch_layout(jobs, n_jobs);
+    if ((rc = check_workspace(workspace, workspace_bytes, L.total))) return rc;
+    return batch_device(jobs, n_jobs, static_cast<char*>(workspace), L,
+                        static_cast<hipStream_t>(hip_stream));
 }
 
 static int checkpoint_interval(int steps, int checkpoint_every) {

@@ -114,7 +114,12 @@ __device__ __attribute__((noinline)) void batch_col(g_float2* work_g, const g_fl
 
 __global__ __launch_bounds__(kBlock) void batch_kernel(const BatchJob* __restrict__ jobs,
                                                        const BatchSeg* __restrict__ segs,
-                                                       int total, unsigned* q) {
+                                                       int total, unsigned* q,
+                                                       const unsigned long long* key_dev,
+                                                       unsigned long long key) {
+    // the tables in the workspace belong to other jobs (or were never
+    // written): take no item, touch nothing
+    if (*key_dev != key) return;
     extern __shared__ float2 smem[];
     lds_float2* lds = (lds_float2*)smem;
     __shared__ int s_item;
@@ -214,7 +219,8 @@ static int device_cus() {
 }
 
 hipError_t launch_batch(const BatchJob* jobs_dev, const BatchSeg* segs_dev, int total,
-                        unsigned* q, int n_jobs, hipStream_t s) {
+                        unsigned* q, int n_jobs, const unsigned long long* key_dev,
+                        unsigned long long key, hipStream_t s) {
     const int words = batch_queue_words(n_jobs);
     batch_zero_kernel<<<(words + 255) / 256, 256, 0, s>>>(q, words);
     hipError_t e = hipGetLastError();
@@ -223,7 +229,7 @@ hipError_t launch_batch(const BatchJob* jobs_dev, const BatchSeg* segs_dev, int 
     if (cus <= 0) return hipErrorNoDevice;
     // every size needs the same LDS: units_per_block * lds_size = 17 * 256 float2
     const size_t lds = sizeof(float2) * units_per_block<1024>() * lds_size<1024>();
-    batch_kernel<<<cus, kBlock, lds, s>>>(jobs_dev, segs_dev, total, q);
+    batch_kernel<<<cus, kBlock, lds, s>>>(jobs_dev, segs_dev, total, q, key_dev, key);
     return hipGetLastError();
 }
 

@@ -89,7 +89,8 @@ int col_units(int nx, int ny);
 int row_items(int nx, int ny);  // work items of one row pass
 int col_items(int nx, int ny);  // work items of one column pass
 hipError_t launch_batch(const BatchJob* jobs_dev, const BatchSeg* segs_dev, int total,
-                        unsigned* q, int n_jobs, hipStream_t s);
+                        unsigned* q, int n_jobs, const unsigned long long* key_dev,
+                        unsigned long long key, hipStream_t s);
 
 // PSF readout of a multiplexed run (readout.hip).
 struct ReadoutArgs {

@@ -136,6 +136,13 @@ def test_batch_validation(L):
     need = L.bpm_batch_workspace_size(jobs, 2)
     assert need > 2 * L.bpm_workspace_size(64, 64, 3, 0)
     assert L.bpm_propagate_batch(jobs, 2, b.p, need - 1, None) == B.BPM_ERR_WORKSPACE
+    # the two halves validate like the whole call (no device work on a bad argument)
+    for half in (L.bpm_batch_upload, L.bpm_batch_launch):
+        assert half(jobs, 2, b.p, need - 1, None) == B.BPM_ERR_WORKSPACE
+        assert half(jobs, 0, b.p, need, None) == B.BPM_ERR_INVALID_ARG
+        bad = (B.Job * 2)(jobs[0], B.Job(b.p, None, 64, 64, 3, 0.2, 0.2, 0.5, 1.33, b.p, 0))
+        assert half(bad, 2, b.p, need, None) == B.BPM_ERR_INVALID_ARG
+        assert b"job 1" in L.bpm_last_error()
 
 
 def test_helper_validation(L):

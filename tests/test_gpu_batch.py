@@ -111,3 +111,53 @@ def test_lockstep_batch_of_one_geometry(shape, n_jobs):
             assert inten is None
         else:
             assert np.array_equal(inten.cpu().numpy(), ref[k][1]), k
+
+
+def test_prepared_batch_in_a_captured_graph():
+    """The device half of the batch (bpm_batch_launch) captured into a graph:
+    three replays, each after new inputs were written into the captured
+    tensors, each equal bit for bit to separate marches of those inputs; and a
+    launch on a workspace that holds no tables leaves the outputs untouched."""
+    import paper_1706_02261_amd as bpm
+    from paper_1706_02261_amd import _lib
+    from paper_1706_02261_amd.bpm import _ptr, _stream_ptr
+    jobs = make_jobs([(64, 128, 5), (256, 256, 7), (32, 32, 0), (128, 64, 4)], seed=21)
+    prep = bpm.PreparedBatch(jobs)
+    first = [(o.clone(), None if i is None else i.clone()) for o, i in prep.launch()]
+    torch.cuda.synchronize()
+    for job, (o, i) in zip(jobs, first):
+        so, si = separate(job)
+        assert np.array_equal(o.cpu().numpy(), so)
+        assert i is None or np.array_equal(i.cpu().numpy(), si)
+    g = torch.cuda.CUDAGraph()
+    with torch.cuda.graph(g):
+        prep.launch()
+    torch.cuda.synchronize()
+    gen = np.random.default_rng(6)
+    for rep in range(3):
+        for job in jobs:
+            ny, nx = job["field"].shape
+            u = gen.standard_normal((ny, nx)) + 1j * gen.standard_normal((ny, nx))
+            job["field"].copy_(torch.from_numpy(u.astype(np.complex64)))
+            job["dn"].copy_(torch.from_numpy(
+                gen.uniform(0, 0.05, tuple(job["dn"].shape)).astype(np.float32)))
+        torch.cuda.synchronize()
+        g.replay()
+        torch.cuda.synchronize()
+        for k, (job, (o, i)) in enumerate(zip(jobs, prep.results)):
+            so, si = separate(job)
+            assert np.array_equal(o.cpu().numpy(), so), (rep, k)
+            assert i is None or np.array_equal(i.cpu().numpy(), si), (rep, k)
+    # a workspace without tables: the batch kernel takes no item
+    for o, i in prep.results:
+        o.fill_(7.0)
+        if i is not None:
+            i.fill_(7.0)
+    empty = torch.zeros_like(prep.ws)
+    rc = _lib.lib().bpm_batch_launch(prep._arr, len(jobs), _ptr(empty), empty.numel(),
+                                     _stream_ptr(None))
+    torch.cuda.synchronize()
+    assert rc == 0
+    for job, (o, i) in zip(jobs, prep.results):
+        if job["dn"].shape[0] > 0:
+            assert bool((o == 7.0).all()) and (i is None or bool((i == 7.0).all()))
