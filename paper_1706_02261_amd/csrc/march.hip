@@ -242,10 +242,14 @@ __global__ __launch_bounds__(kBlock, OCC) void march_kernel(MarchArgs a) {
 //
 //   1. forward march from u_0 keeping u at every K-th slice boundary;
 //   2. for each segment of K steps, last to first: recompute the segment's
-//      fields from its checkpoint (kept in `seg`), then run its adjoint steps
-//      backwards; the adjoint state crosses segments in `gwork`;
+//      fields from its checkpoint (kept in one of two `seg` buffers), then
+//      run its adjoint steps backwards; the recompute of the segment before
+//      shares the passes of these adjoint steps; the adjoint state crosses
+//      segments in `gwork`;
 //   3. a tail row pass brings g_0 back to natural order.
-// Memory: (ceil(N/K) + K + 2) fields; compute: about three forward marches.
+// Memory: ceil(N/K) + 2 K + 2 fields (K + 2 more than the checkpoints and
+// one segment); compute: about three forward marches in about two marches'
+// worth of passes.
 
 struct AdjointArgs {
     const float2* field_in;
@@ -258,7 +262,7 @@ struct AdjointArgs {
     float2* fwork;
     float2* gwork;
     float2* ckpt;  // [ceil(N/K)] fields (slot 0 unused: u_0 is field_in)
-    float2* seg;   // [K] fields
+    float2* seg;   // [2 K] fields: two segment buffers
     const float2* H;
     const float2* twx;
     const float2* twy;
@@ -320,47 +324,73 @@ __global__ __launch_bounds__(BLK) void adjoint_kernel(AdjointArgs a) {
         }
     }
 
-    // 2. segments, last to first
-    for (int c = C - 1; c >= 0; --c) {
-        const int start = c * K, L = (N - start) < K ? (N - start) : K;
-        grid_sync(a.counter, ++nbar, abort);
-        RowArgs fr{c == 0 ? a.field_in : a.ckpt + (size_t)c * plane, a.fwork, nullptr, nullptr,
-                   nullptr, nullptr, nullptr, a.k0dz};
-        for (int u = v; u < rows_u; u += G)
+    // 2. segments, last to first.  Recomputing segment c from its checkpoint
+    // takes 2 L + 1 passes (the head row pass to the spectrum, then a column
+    // and a row pass per step, the row passes keeping u in segment buffer
+    // c % 2); its adjoint steps take 2 L passes (a row and a column pass per
+    // step, last step first) and read that buffer.  The recompute of segment
+    // c - 1 runs in the same passes as the adjoint steps of segment c (the
+    // other buffer, the other work field), so one grid barrier serves both.
+    auto seg_of = [&](int c) { return a.seg + (size_t)(c & 1) * K * plane; };
+    auto len_of = [&](int c) { return N - c * K < K ? N - c * K : K; };
+    // units of pass i: recompute: 0 head row, odd column, even row;
+    // adjoint: even row, odd column
+    auto rec_units = [&](int i) { return i % 2 == 0 ? rows_u : cols_u; };
+    auto adj_units = [&](int i) { return i % 2 == 0 ? rows_u : cols_u; };
+    auto rec_unit = [&](int c, int i, int u) {
+        if (i == 0) {
+            RowArgs fr{c == 0 ? a.field_in : a.ckpt + (size_t)c * plane, a.fwork, nullptr,
+                       nullptr, nullptr, nullptr, nullptr, a.k0dz};
             row_unit<NX, kNaturalIn, kNoOps, kSpecOut, BLK>(u, a.ny, fr, d, twx, smem);
-        fr.src = a.fwork;
-        for (int s = 0; s < L; ++s) {
-            grid_sync(a.counter, ++nbar, abort);
-            col_pass(a.fwork, false, nullptr);
-            grid_sync(a.counter, ++nbar, abort);
-            fr.keep = a.seg + (size_t)s * plane;
-            for (int u = v; u < rows_u; u += G) {
-                load_dn<NX, BLK>(d, u, a.ny, a.dn + (start + s) * plane);
-                if (s + 1 < L)
-                    row_unit<NX, kSpecIn, kScreen, kSpecOut, BLK>(u, a.ny, fr, d, twx, smem);
-                else
-                    row_unit<NX, kSpecIn, kScreen, kNoOut, BLK>(u, a.ny, fr, d, twx, smem);
-            }
+        } else if (i % 2 == 1) {
+            col_unit<NY, false, BLK>(u, a.nx, a.fwork, a.H, twy, smem, nullptr, nullptr, nullptr);
+        } else {
+            const int t = i / 2 - 1;
+            RowArgs fr{a.fwork, a.fwork, nullptr, seg_of(c) + (size_t)t * plane, nullptr,
+                       nullptr, nullptr, a.k0dz};
+            load_dn<NX, BLK>(d, u, a.ny, a.dn + (size_t)(c * K + t) * plane);
+            if (t + 1 < len_of(c))
+                row_unit<NX, kSpecIn, kScreen, kSpecOut, BLK>(u, a.ny, fr, d, twx, smem);
+            else
+                row_unit<NX, kSpecIn, kScreen, kNoOut, BLK>(u, a.ny, fr, d, twx, smem);
         }
-        for (int s = L - 1; s >= 0; --s) {
-            const int j = start + s;
-            RowArgs br{a.gwork, a.gwork, nullptr, nullptr, a.seg + (size_t)s * plane,
-                       a.gI ? a.gI + j * plane : nullptr, a.gdn ? a.gdn + j * plane : nullptr,
-                       a.k0dz};
-            grid_sync(a.counter, ++nbar, abort);
-            for (int u = v; u < rows_u; u += G) {
-                load_dn<NX, BLK>(d, u, a.ny, a.dn + j * plane);
-                if (j + 1 < N) {
-                    row_unit<NX, kSpecIn, kAdjointOps, kSpecOut, BLK>(u, a.ny, br, d, twx, smem);
-                } else if (a.gout) {
-                    br.src = a.gout;
-                    row_unit<NX, kNaturalIn, kAdjointOps, kSpecOut, BLK>(u, a.ny, br, d, twx, smem);
-                } else {
-                    row_unit<NX, kZeroIn, kAdjointOps, kSpecOut, BLK>(u, a.ny, br, d, twx, smem);
-                }
+    };
+    auto adj_unit = [&](int c, int i, int u) {
+        const int s = len_of(c) - 1 - i / 2, j = c * K + s;
+        if (i % 2 == 0) {
+            RowArgs br{a.gwork, a.gwork, nullptr, nullptr, seg_of(c) + (size_t)s * plane,
+                       a.gI ? a.gI + (size_t)j * plane : nullptr,
+                       a.gdn ? a.gdn + (size_t)j * plane : nullptr, a.k0dz};
+            load_dn<NX, BLK>(d, u, a.ny, a.dn + (size_t)j * plane);
+            if (j + 1 < N) {
+                row_unit<NX, kSpecIn, kAdjointOps, kSpecOut, BLK>(u, a.ny, br, d, twx, smem);
+            } else if (a.gout) {
+                br.src = a.gout;
+                row_unit<NX, kNaturalIn, kAdjointOps, kSpecOut, BLK>(u, a.ny, br, d, twx, smem);
+            } else {
+                row_unit<NX, kZeroIn, kAdjointOps, kSpecOut, BLK>(u, a.ny, br, d, twx, smem);
             }
+        } else {
+            col_unit<NY, true, BLK>(u, a.nx, a.gwork, a.H, twy, smem, j == 0 ? a.gspec : nullptr,
+                                    a.permx, a.permy);
+        }
+    };
+    // the last segment's recompute alone, then adjoint c with recompute c - 1
+    for (int i = 0; i < 2 * len_of(C - 1) + 1; ++i) {
+        grid_sync(a.counter, ++nbar, abort);
+        for (int u = v; u < rec_units(i); u += G) rec_unit(C - 1, i, u);
+    }
+    for (int c = C - 1; c >= 0; --c) {
+        const int PA = 2 * len_of(c), PR = c > 0 ? 2 * len_of(c - 1) + 1 : 0;
+        for (int i = 0; i < (PA > PR ? PA : PR); ++i) {
             grid_sync(a.counter, ++nbar, abort);
-            col_pass(a.gwork, true, j == 0 ? a.gspec : nullptr);
+            const int na = i < PA ? adj_units(i) : 0, nr = i < PR ? rec_units(i) : 0;
+            for (int u = v; u < na + nr; u += G) {
+                if (u < na)
+                    adj_unit(c, i, u);
+                else
+                    rec_unit(c - 1, i, u - na);
+            }
         }
     }
 
@@ -573,7 +603,7 @@ hipError_t launch_forward(const Geom& g, const Plan& p, const MarchIO* io, int f
 
 size_t adjoint_fields(int steps, int K) {
     const int C = (steps + K - 1) / K;
-    return (size_t)C + K + 2;
+    return (size_t)C + 2 * (size_t)K + 2;
 }
 
 hipError_t launch_adjoint(const Geom& g, const Plan& p, const AdjointIO& io, int K, void* fields,
@@ -594,7 +624,7 @@ hipError_t launch_adjoint(const Geom& g, const Plan& p, const AdjointIO& io, int
         void* args[] = {&a};
         return hipLaunchCooperativeKernel(
             reinterpret_cast<const void*>(&adjoint_kernel<NX, NY, BLK>),
-            dim3(persistent_grid<NX, NY, BLK>(g.nx, g.ny)), dim3(BLK), args,
+            dim3(persistent_grid<NX, NY, BLK>(g.nx, g.ny, 2)), dim3(BLK), args,
             (unsigned)persistent_lds<NX, NY, BLK>(), s);
     });
 }

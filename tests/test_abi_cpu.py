@@ -60,7 +60,7 @@ def test_workspace_sizes(L):
     assert fwd >= 8 * 1024 * 1024                      # the propagator table
     adj = L.bpm_adjoint_workspace_size(256, 256, 512, 0)
     k = math.ceil(math.sqrt(512))
-    fields = math.ceil(512 / k) + k + 2
+    fields = math.ceil(512 / k) + 2 * k + 2            # checkpoints, two segment buffers
     assert adj >= fields * 256 * 256 * 8
     assert L.bpm_workspace_size(256, 256, 512, 1) == adj
     assert L.bpm_adjoint_workspace_size(256, 256, 512, 513) == 0
