@@ -50,8 +50,10 @@ def gpu_adjoint(u0, dn, w, gI, dx=0.2, dz=0.2, ck=0):
     return cpu(g0), cpu(gs), cpu(gdn)
 
 
-@pytest.mark.parametrize("nx,ny,steps", [(64, 128, 10), (128, 32, 7), (256, 256, 33), (32, 64, 1)])
+@pytest.mark.parametrize("nx,ny,steps", [(64, 128, 10), (128, 32, 7), (256, 256, 33), (32, 64, 1),
+                                         (1024, 64, 6), (64, 1024, 5)])
 def test_adjoint_parity(nx, ny, steps):
+    """Oracle gradients; sides above 512 take the 256-thread-workgroup kernel."""
     u0, w, gI, dn = rand_case(nx, ny, steps, seed=nx + ny + steps)
     g0, gs, gdn = gpu_adjoint(u0, dn, w, gI)
     r0, rs, rdn = oracle.bpm_adjoint(u0, dn, 0.2, 0.2, LAM, N0, grad_u_out=w, grad_intensity=gI)
@@ -75,10 +77,13 @@ def test_adjoint_zero_steps():
     assert rel(gs, np.fft.fft2(w.astype(complex)) / w.size) <= 1e-6
 
 
-def test_checkpoint_interval_is_bitwise_invariant():
-    u0, w, gI, dn = rand_case(128, 128, 20, seed=6)
+@pytest.mark.parametrize("nx,ny,steps", [(128, 128, 20), (1024, 64, 10)])
+def test_checkpoint_interval_is_bitwise_invariant(nx, ny, steps):
+    """Every checkpoint interval, including a shorter last segment and a
+    single segment, gives the same bits."""
+    u0, w, gI, dn = rand_case(nx, ny, steps, seed=6)
     ref = gpu_adjoint(u0, dn, w, gI, ck=0)
-    for ck in (1, 3, 7, 20):
+    for ck in sorted({1, 3, 7, steps}):
         got = gpu_adjoint(u0, dn, w, gI, ck=ck)
         for a, b in zip(got, ref):
             assert np.array_equal(a, b), f"checkpoint_every={ck}"
