@@ -12,6 +12,8 @@
 // D[8 (i / 4) + 4 (l / 32) + i % 4][l % 32].
 #include <hip/hip_runtime.h>
 
+#include <type_traits>
+
 #include "internal.hpp"
 
 namespace bpm {
@@ -87,32 +89,71 @@ __global__ __launch_bounds__(256) void conv_fwd_kernel(const void* __restrict__ 
     const int iz0 = oz * c.sd - c.pd, iy0 = oy0 * c.sh - c.ph, ix0 = -c.pw;
     const int cch = c.Ci / 8;
     const int total = c.kd * t.FY * t.FX * cch;
-    for (int e = threadIdx.x; e < total; e += 256) {
+    // staging: each thread issues the loads of up to kStageBatch chunks before
+    // it writes any of them to LDS, so their memory latencies overlap
+    constexpr int kStageBatch = 8;
+    using Raw = typename std::conditional<IN == kInPatch, float, uint4>::type;
+    auto voxel = [&](int e, int& c8, int& iz, int& iy, int& ix, int& slot) {
         int q = e;
-        const int c8 = q % cch;
+        c8 = q % cch;
         q /= cch;
         const int fx = q % t.FX;
         q /= t.FX;
         const int fy = q % t.FY, fz = q / t.FY;
-        const int iz = iz0 + fz, iy = iy0 + fy, ix = ix0 + fx;
-        uint4 v = make_uint4(0, 0, 0, 0);
-        if ((unsigned)iz < (unsigned)c.D && (unsigned)iy < (unsigned)c.H &&
-            (unsigned)ix < (unsigned)c.W) {
-            if constexpr (IN == kInBf16) {
-                const u16* xn = static_cast<const u16*>(xin) + (size_t)n * c.D * c.H * c.W * c.Ci;
-                v = *reinterpret_cast<const uint4*>(
-                    xn + (((size_t)iz * c.H + iy) * c.W + ix) * c.Ci + c8 * 8);
-            } else if constexpr (IN == kInPatch) {
-                const float* dn = static_cast<const float*>(xin) + (size_t)n * c.D * c.H * c.W;
-                v = input_channels(dn[((size_t)iz * c.H + iy) * c.W + ix], depth[n], iz, iy, ix);
+        iz = iz0 + fz;
+        iy = iy0 + fy;
+        ix = ix0 + fx;
+        slot = ((fz * t.FY + fy) * t.FX + fx) * t.CiP + c8 * 8;
+        return (unsigned)iz < (unsigned)c.D && (unsigned)iy < (unsigned)c.H &&
+               (unsigned)ix < (unsigned)c.W;
+    };
+    for (int e0 = threadIdx.x; e0 < total; e0 += 256 * kStageBatch) {
+        Raw raw[kStageBatch];
+        bool inb[kStageBatch];
+#pragma unroll
+        for (int i = 0; i < kStageBatch; ++i) {
+            const int e = e0 + 256 * i;
+            int c8, iz, iy, ix, slot;
+            inb[i] = e < total && voxel(e, c8, iz, iy, ix, slot);
+            if constexpr (IN == kInPatch) {
+                raw[i] = 0.f;
+                if (inb[i]) {
+                    const float* dn =
+                        static_cast<const float*>(xin) + (size_t)n * c.D * c.H * c.W;
+                    raw[i] = dn[((size_t)iz * c.H + iy) * c.W + ix];
+                }
+            } else if constexpr (IN == kInBf16) {
+                raw[i] = make_uint4(0, 0, 0, 0);
+                if (inb[i]) {
+                    const u16* xn =
+                        static_cast<const u16*>(xin) + (size_t)n * c.D * c.H * c.W * c.Ci;
+                    raw[i] = *reinterpret_cast<const uint4*>(
+                        xn + (((size_t)iz * c.H + iy) * c.W + ix) * c.Ci + c8 * 8);
+                }
             } else {
-                const int h2 = c.H / 2, w2 = c.W / 2;
-                const u16* xn = static_cast<const u16*>(xin) + (size_t)n * c.D * h2 * w2 * c.Ci;
-                v = *reinterpret_cast<const uint4*>(
-                    xn + (((size_t)iz * h2 + iy / 2) * w2 + ix / 2) * c.Ci + c8 * 8);
+                raw[i] = make_uint4(0, 0, 0, 0);
+                if (inb[i]) {
+                    const int h2 = c.H / 2, w2 = c.W / 2;
+                    const u16* xn =
+                        static_cast<const u16*>(xin) + (size_t)n * c.D * h2 * w2 * c.Ci;
+                    raw[i] = *reinterpret_cast<const uint4*>(
+                        xn + (((size_t)iz * h2 + iy / 2) * w2 + ix / 2) * c.Ci + c8 * 8);
+                }
             }
         }
-        *reinterpret_cast<uint4*>(xs + ((fz * t.FY + fy) * t.FX + fx) * t.CiP + c8 * 8) = v;
+#pragma unroll
+        for (int i = 0; i < kStageBatch; ++i) {
+            const int e = e0 + 256 * i;
+            if (e >= total) break;
+            int c8, iz, iy, ix, slot;
+            voxel(e, c8, iz, iy, ix, slot);
+            uint4 v;
+            if constexpr (IN == kInPatch)
+                v = inb[i] ? input_channels(raw[i], depth[n], iz, iy, ix) : make_uint4(0, 0, 0, 0);
+            else
+                v = raw[i];
+            *reinterpret_cast<uint4*>(xs + slot) = v;
+        }
     }
     // after the tile: the LDS offset of every 8-channel chunk of the reduction
     // index relative to a position's tap (0, 0, 0) voxel (-1: zero padding of
