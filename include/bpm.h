@@ -261,6 +261,47 @@ int psf_surrogate_infer(const void* weights_bf16, size_t weights_bytes,
                         float* psf_out, float* pred_err, void* workspace,
                         size_t workspace_bytes, void* hip_stream);
 
+/* Wait time-outs of the persistent kernels.
+ *
+ * The persistent kernels of bpm_propagate, bpm_propagate_batch,
+ * bpm_batch_launch and bpm_adjoint wait for each other (grid barriers between
+ * the passes of a march; per-job dependency waits in the uneven batch).  Every
+ * wait is bounded: a wait that has polled `polls` times gives up, the kernel
+ * stops waiting from then on and runs to its end, and its outputs are NOT
+ * valid.  This only happens when the workgroups of a launch cannot all run
+ * (another process holding the device's compute units, a misbehaving driver);
+ * the default bound (2^22 polls, tens of milliseconds per wait) is far above
+ * any regular wait.
+ *
+ * Such a time-out is recorded in the workspace: the first 256 bytes of every
+ * workspace of the calls above form a status header whose 32-bit word 0 is a
+ * sticky mask (bit 0: a grid-barrier wait gave up; bit 1: a work-queue
+ * dependency wait gave up), set by the kernels and never cleared by them.
+ * (Words 1 and 2 mark the header as initialised; the first call on a fresh
+ * workspace clears word 0.)  The calls themselves are asynchronous and
+ * return before their kernels run, so they cannot report it; query it with
+ * bpm_workspace_status. */
+
+/* Synchronises hip_stream, reads the status header of `workspace` and resets
+ * its mask.  Returns BPM_OK when no wait gave up since the previous query (or
+ * since the workspace's first call), BPM_ERR_DEVICE with a message naming the
+ * kind of wait otherwise, BPM_ERR_INVALID_ARG when no march, batch or adjoint
+ * call has used the workspace or the stream is capturing, BPM_ERR_WORKSPACE
+ * for a null, misaligned or short (< 256 bytes) workspace.  Must not be called
+ * while a call that uses the same workspace may still be queued on another
+ * stream. */
+int bpm_workspace_status(const void* workspace, size_t workspace_bytes, void* hip_stream);
+
+/* Maps a status mask (word 0 of the header, e.g. copied to the host by the
+ * caller's own stream-ordered copy) to BPM_OK (0) or BPM_ERR_DEVICE with the
+ * message bpm_workspace_status would give.  Host only; touches no device. */
+int bpm_decode_status(unsigned status_word);
+
+/* Process-wide bound on the polls of one wait (see above); 0 restores the
+ * default 2^22, values above 2^31 return BPM_ERR_INVALID_ARG.  Applies to
+ * kernels launched after the call. */
+int bpm_set_wait_limit(unsigned long long polls);
+
 /* Static text for an error code. */
 const char* bpm_error_string(int code);
 /* Message of the calling thread's last failed call ("" if none). */

@@ -25,9 +25,18 @@ gradient handed to the layer below.  Arithmetic stays float64.  With
 ``rnd=False`` the network is a smooth float64 function (finite-difference
 pins).
 
-Parity status: pinned by central finite differences of the loss in float64
-(tests/test_oracle_surrogate_net.py); the convolutions themselves are pinned
-in tests/test_oracle_conv.py.
+The optimizer step ``adam_step`` is Adam (Kingma & Ba, "Adam: a method for
+stochastic optimization", ICLR 2015, Algorithm 1): exponential moving
+averages of the gradient and of its square, each divided by its bias
+correction, then w -= lr m_hat / (sqrt(v_hat) + eps).
+
+Parity status: the network is pinned by central finite differences of the
+loss in float64 (tests/test_oracle_surrogate_net.py); the convolutions
+themselves are pinned in tests/test_oracle_conv.py; ``adam_step`` by the
+closed form of the first step from zero moments, by constant gradients
+(bias-corrected moments exact at every step), by the unrolled sums of the
+moment recursions and by convergence on a quadratic
+(tests/test_oracle_adam.py).
 """
 from __future__ import annotations
 
@@ -146,3 +155,17 @@ def backward(params, cache, target, lam, rnd=True):
         if l > 0:
             dz = rb(dx * (cache["acts"][l] > 0))
     return grads
+
+
+def adam_step(w, g, m, v, t, lr, beta1=0.9, beta2=0.999, eps=1e-8):
+    """One Adam update at step t >= 1 (Kingma & Ba 2015, Algorithm 1), float64.
+
+    Returns (w_new, m_new, v_new); inputs are not modified."""
+    if t < 1:
+        raise ValueError("Adam steps are counted from 1")
+    w, g = np.asarray(w, np.float64), np.asarray(g, np.float64)
+    m = beta1 * np.asarray(m, np.float64) + (1.0 - beta1) * g
+    v = beta2 * np.asarray(v, np.float64) + (1.0 - beta2) * g * g
+    m_hat = m / (1.0 - beta1 ** t)
+    v_hat = v / (1.0 - beta2 ** t)
+    return w - lr * m_hat / (np.sqrt(v_hat) + eps), m, v

@@ -35,6 +35,7 @@ EXPORTS = (
     "psf_conv_workspace_size", "psf_conv_forward", "psf_conv_backward",
     "psf_surrogate_layer_geometry", "psf_extract_patches",
     "bpm_point_sources_workspace_size", "bpm_point_sources",
+    "bpm_workspace_status", "bpm_decode_status", "bpm_set_wait_limit",
 )
 
 
@@ -117,6 +118,12 @@ def _declare(L):
     L.bpm_psf_readout.argtypes = [_V, _I, _I, _D, _D, _D, _D, _D, _I, _V, _I, _I, _I, _D, _V,
                                   _V, _Z, _V]
     L.bpm_psf_readout.restype = _I
+    L.bpm_workspace_status.argtypes = [_V, _Z, _V]
+    L.bpm_workspace_status.restype = _I
+    L.bpm_decode_status.argtypes = [ctypes.c_uint]
+    L.bpm_decode_status.restype = _I
+    L.bpm_set_wait_limit.argtypes = [ctypes.c_ulonglong]
+    L.bpm_set_wait_limit.restype = _I
     L.bpm_error_string.argtypes = [_I]
     L.bpm_error_string.restype = _S
     L.bpm_last_error.argtypes = []

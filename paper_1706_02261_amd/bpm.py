@@ -77,6 +77,20 @@ def propagate(field: torch.Tensor, dn: torch.Tensor, dx: float, dz: float,
     return out, intensity_out
 
 
+def workspace_status(ws: torch.Tensor, stream=None) -> None:
+    """Raise BpmError (BPM_ERR_DEVICE) if a wait of a kernel that used ``ws``
+    gave up since the last query (its outputs are not valid); synchronises the
+    stream and resets the record."""
+    _need(ws, "ws", torch.uint8)
+    check(lib().bpm_workspace_status(_ptr(ws), ws.numel(), _stream_ptr(stream)),
+          "bpm_workspace_status")
+
+
+def set_wait_limit(polls: int = 0) -> None:
+    """Bound on the polls of one grid-barrier or queue wait (0: the default)."""
+    check(lib().bpm_set_wait_limit(int(polls)), "bpm_set_wait_limit")
+
+
 def adjoint_workspace_size(nx: int, ny: int, steps: int, checkpoint_every: int = 0) -> int:
     n = lib().bpm_adjoint_workspace_size(nx, ny, steps, checkpoint_every)
     if n == 0:

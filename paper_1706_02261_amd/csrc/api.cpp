@@ -6,6 +6,7 @@
 #include <cstdint>
 #include <cstdio>
 #include <algorithm>
+#include <atomic>
 #include <cstring>
 #include <mutex>
 #include <string>
@@ -47,7 +48,63 @@ int check_field_ptrs(const void* in, const float* dn, int steps, const void* out
 
 }  // namespace
 
+namespace bpm {
+
+constexpr unsigned kDefaultWaitLimit = 1u << 22;
+static std::atomic<unsigned> g_wait_limit{kDefaultWaitLimit};
+unsigned wait_limit() { return g_wait_limit.load(std::memory_order_relaxed); }
+
+}  // namespace bpm
+
 extern "C" {
+
+int bpm_set_wait_limit(unsigned long long polls) {
+    if (polls > (1ull << 31))
+        return fail(BPM_ERR_INVALID_ARG, "polls=%llu must be at most 2^31", polls);
+    bpm::g_wait_limit.store(polls == 0 ? bpm::kDefaultWaitLimit : (unsigned)polls,
+                            std::memory_order_relaxed);
+    return BPM_OK;
+}
+
+int bpm_decode_status(unsigned status_word) {
+    if (status_word == 0) return BPM_OK;
+    std::string what;
+    if (status_word & bpm::kStatusBarrierBit) what += " a grid-barrier wait;";
+    if (status_word & bpm::kStatusQueueBit) what += " a work-queue dependency wait;";
+    if (status_word & ~(bpm::kStatusBarrierBit | bpm::kStatusQueueBit))
+        what += " unknown status bits;";
+    what.pop_back();
+    return fail(BPM_ERR_DEVICE,
+                "a kernel that used this workspace gave up waiting (%s): the outputs of that "
+                "call are not valid (status word 0x%x)", what.c_str() + 1, status_word);
+}
+
+int bpm_workspace_status(const void* workspace, size_t workspace_bytes, void* hip_stream) {
+    if (!workspace || workspace_bytes < bpm::kStatusBytes || !aligned(workspace, bpm::kAlign))
+        return fail(BPM_ERR_WORKSPACE,
+                    "workspace must be non-null, %zu-byte aligned and hold at least %zu bytes",
+                    bpm::kAlign, bpm::kStatusBytes);
+    hipStream_t s = static_cast<hipStream_t>(hip_stream);
+    hipStreamCaptureStatus cs = hipStreamCaptureStatusNone;
+    int rc;
+    if ((rc = device_status(hipStreamIsCapturing(s, &cs), "workspace status"))) return rc;
+    if (cs != hipStreamCaptureStatusNone)
+        return fail(BPM_ERR_INVALID_ARG, "bpm_workspace_status must not run under stream capture");
+    unsigned words[3] = {0u, 0u, 0u};
+    hipError_t e = hipMemcpyAsync(words, workspace, sizeof words, hipMemcpyDeviceToHost, s);
+    if (e == hipSuccess) e = hipStreamSynchronize(s);
+    if ((rc = device_status(e, "workspace status"))) return rc;
+    if (words[1] != bpm::kStatusMagic0 || words[2] != bpm::kStatusMagic1)
+        return fail(BPM_ERR_INVALID_ARG,
+                    "the workspace holds no status header: no march, batch or adjoint call has "
+                    "used it");
+    if (words[0] == 0) return BPM_OK;
+    const unsigned zero = 0u;
+    e = hipMemcpyAsync(const_cast<void*>(workspace), &zero, sizeof zero, hipMemcpyHostToDevice, s);
+    if (e == hipSuccess) e = hipStreamSynchronize(s);
+    if ((rc = device_status(e, "workspace status reset"))) return rc;
+    return bpm_decode_status(words[0]);
+}
 
 const char* bpm_error_string(int code) {
     switch (code) {
@@ -282,11 +339,13 @@ int batch_device(const bpm_job* jobs, int n_jobs, char* ws, const BatchLayout& L
             if ((rc = device_status(e, "batch copy"))) return rc;
         }
     }
+    // the first plan's status header opens the workspace
+    unsigned* status = (unsigned*)bpm::plan_carve(ws + L.plan_off[0], jobs[0].nx, jobs[0].ny).status;
     return device_status(bpm::launch_batch((const bpm::BatchJob*)(ws + L.jobs_off),
                                            (const bpm::BatchSeg*)(ws + L.segs_off), L.n_items,
                                            (unsigned*)(ws + L.q_off), n_jobs,
                                            (const unsigned long long*)(ws + L.key_off),
-                                           batch_key(jobs, n_jobs, ws), s),
+                                           batch_key(jobs, n_jobs, ws), status, s),
                          "batch march");
 }
 

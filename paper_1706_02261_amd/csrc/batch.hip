@@ -116,7 +116,8 @@ __global__ __launch_bounds__(kBlock) void batch_kernel(const BatchJob* __restric
                                                        const BatchSeg* __restrict__ segs,
                                                        int total, unsigned* q,
                                                        const unsigned long long* key_dev,
-                                                       unsigned long long key) {
+                                                       unsigned long long key, unsigned* status,
+                                                       unsigned limit) {
     // the tables in the workspace belong to other jobs (or were never
     // written): take no item, touch nothing
     if (*key_dev != key) return;
@@ -144,8 +145,9 @@ __global__ __launch_bounds__(kBlock) void batch_kernel(const BatchJob* __restric
             while (__hip_atomic_load(done, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) <
                    (unsigned)sg.need) {
                 __builtin_amdgcn_s_sleep(1);
-                if (++spins > kSpinLimit) {
+                if (++spins > limit) {
                     __hip_atomic_store(q + 16, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+                    record_timeout(status, kStatusQueue);
                     abort = true;
                     break;
                 }
@@ -210,17 +212,10 @@ __global__ __launch_bounds__(kBlock) void batch_kernel(const BatchJob* __restric
 
 int batch_queue_words(int n_jobs) { return 32 * (n_jobs + 1); }
 
-static int device_cus() {
-    int dev = 0, cus = 0;
-    if (hipGetDevice(&dev) != hipSuccess ||
-        hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess)
-        return 0;
-    return cus;
-}
 
 hipError_t launch_batch(const BatchJob* jobs_dev, const BatchSeg* segs_dev, int total,
                         unsigned* q, int n_jobs, const unsigned long long* key_dev,
-                        unsigned long long key, hipStream_t s) {
+                        unsigned long long key, unsigned* status, hipStream_t s) {
     const int words = batch_queue_words(n_jobs);
     batch_zero_kernel<<<(words + 255) / 256, 256, 0, s>>>(q, words);
     hipError_t e = hipGetLastError();
@@ -229,7 +224,8 @@ hipError_t launch_batch(const BatchJob* jobs_dev, const BatchSeg* segs_dev, int 
     if (cus <= 0) return hipErrorNoDevice;
     // every size needs the same LDS: units_per_block * lds_size = 17 * 256 float2
     const size_t lds = sizeof(float2) * units_per_block<1024>() * lds_size<1024>();
-    batch_kernel<<<cus, kBlock, lds, s>>>(jobs_dev, segs_dev, total, q, key_dev, key);
+    batch_kernel<<<cus, kBlock, lds, s>>>(jobs_dev, segs_dev, total, q, key_dev, key, status,
+                                          wait_limit());
     return hipGetLastError();
 }
 

@@ -21,6 +21,7 @@ struct Geom {
 // the twiddle tables tw[e] = exp(-2 pi i e / n), the storage-slot ->
 // frequency tables of both axes and the grid-barrier words.
 struct Plan {
+    void* status;   // status header (kStatusBytes): [0] sticky time-out bits, [1..2] magic
     void* H;        // float2 [ny][nx]
     void* twx;      // float2 [nx]
     void* twy;      // float2 [ny]
@@ -28,7 +29,18 @@ struct Plan {
     void* permy;    // int [ny]
     void* counter;  // grid-barrier words and time-out flag (4 KiB, zeroed by the plan)
 };
+// Every plan, and so every march-family workspace, starts with this header;
+// the plan kernel initialises it once (when its magic is absent) and never
+// clears the sticky bits, which only bpm_workspace_status reads and resets.
+constexpr size_t kStatusBytes = 256;
+constexpr unsigned kStatusMagic0 = 0x4d50425fu, kStatusMagic1 = 0x53555441u;
+// host copies of the sticky bits the kernels set (passes.hpp)
+constexpr unsigned kStatusBarrierBit = 1u, kStatusQueueBit = 2u;
+// polls of one grid-barrier or queue wait before a kernel gives up
+unsigned wait_limit();
 size_t plan_bytes(int nx, int ny);
+// compute units of the current device (0 when the query fails)
+int device_cus();
 Plan plan_carve(void* ws, int nx, int ny);
 hipError_t launch_plan(const Geom& g, const Plan& p, bool with_h, hipStream_t s);
 
@@ -90,7 +102,7 @@ int row_items(int nx, int ny);  // work items of one row pass
 int col_items(int nx, int ny);  // work items of one column pass
 hipError_t launch_batch(const BatchJob* jobs_dev, const BatchSeg* segs_dev, int total,
                         unsigned* q, int n_jobs, const unsigned long long* key_dev,
-                        unsigned long long key, hipStream_t s);
+                        unsigned long long key, unsigned* status, hipStream_t s);
 
 // PSF readout of a multiplexed run (readout.hip).
 struct ReadoutArgs {

@@ -1,0 +1,375 @@
+// Kernel templates of the persistent marches (forward and adjoint) and their
+// launchers, instantiated once per row length NX in march_x<NX>.hip so that
+// the seven lengths compile in parallel.  See march.hip for the pass
+// structure of one step.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <type_traits>
+
+#include "internal.hpp"
+#include "passes.hpp"
+
+namespace bpm {
+
+// ---------------------------------------------------------------------------
+// persistent forward march
+
+// LDS of one workgroup's row or column unit (the larger of the two)
+template <int NX, int NY>
+__host__ __device__ constexpr size_t march_data_lds() {
+    return sizeof(float2) * (units_per_block<NX>() * lds_size<NX>() >
+                                     units_per_block<NY>() * lds_size<NY>()
+                                 ? units_per_block<NX>() * lds_size<NX>()
+                                 : units_per_block<NY>() * lds_size<NY>());
+}
+
+// Up to kMaxFields marches of one geometry run in lockstep: every pass covers
+// the units of all fields, so the two grid barriers of a step are shared and a
+// workgroup's loads and stores of one unit overlap the work on the next.
+struct MarchArgs {
+    const float2* field_in[kMaxFields];
+    float2* work[kMaxFields];
+    const float* dn[kMaxFields];
+    float* inten[kMaxFields];
+    const float2* H;
+    const float2* twx;
+    const float2* twy;
+    unsigned* counter;
+    unsigned* status;  // the workspace's sticky status word
+    unsigned limit;    // polls of one barrier wait before it gives up
+    int nx, ny, steps, fields;
+    float k0dz;
+};
+
+// OCC = workgroups per CU.  OCC 1 keeps the twiddles in registers and walks
+// a workgroup's units two at a time (the second unit's loads in flight while
+// the first is transformed).  OCC 2 (several fields) reads the twiddles from
+// tables in LDS instead, so that two workgroups fit one CU (two waves per
+// SIMD) and one workgroup's memory waits overlap the other's arithmetic.
+template <int NX, int NY, int OCC>
+__global__ __launch_bounds__(kBlock, OCC) void march_kernel(MarchArgs a) {
+    extern __shared__ float2 smem[];
+    const int G = gridDim.x, v = virtual_block();
+    const int rows_u = (a.ny + units_per_block<NX>() - 1) / units_per_block<NX>();
+    const int cols_u = (a.nx + units_per_block<NY>() - 1) / units_per_block<NY>();
+    const int all_r = rows_u * a.fields, all_c = cols_u * a.fields;
+    const size_t plane = (size_t)a.nx * a.ny;
+    unsigned nbar = 0;
+    bool abort = false;
+    using TwX = typename std::conditional<OCC == 1, Twiddles<NX, kR>, LdsTwiddles<NX, kR>>::type;
+    using TwY = typename std::conditional<OCC == 1, Twiddles<NY, kR>, LdsTwiddles<NY, kR>>::type;
+    TwX twx;
+    TwY twy;
+    if constexpr (OCC == 1) {
+        twx.load(a.twx, threadIdx.x % (NX / kR));
+        twy.load(a.twy, threadIdx.x / units_per_block<NY>());
+    } else {
+        float2* tabx = smem + march_data_lds<NX, NY>() / sizeof(float2);
+        float2* taby = tabx + NX;
+        for (int i = threadIdx.x; i < NX; i += kBlock) tabx[i] = a.twx[i];
+        for (int i = threadIdx.x; i < NY; i += kBlock) taby[i] = a.twy[i];
+        __syncthreads();
+        twx = TwX{tabx, (int)threadIdx.x % (NX / kR)};
+        twy = TwY{taby, (int)threadIdx.x / units_per_block<NY>()};
+    }
+    constexpr int PAIR = OCC == 1 ? 2 : 1;  // units per loop trip
+    float d[kR];
+    for (int i = 0; i < kR; ++i) d[i] = 0.f;
+    // combined unit u is unit u / fields of field u % fields: the fields'
+    // units of one column range sit next to each other, so the workgroups of
+    // an XCD share that range's slice of the propagator table in its L2
+    const int F = a.fields;
+    for (int u = v; u < all_r; u += G) {
+        const int f = u % F;
+        RowArgs ra{a.field_in[f], a.work[f], nullptr, nullptr, nullptr, nullptr, nullptr, a.k0dz};
+        row_unit<NX, kNaturalIn, kNoOps, kSpecOut>(u / F, a.ny, ra, d, twx, smem);
+    }
+    // a workgroup with a single row unit fetches its dn slice during the column pass
+    const bool one_row_unit = all_r <= G;
+    const int vv = v < all_r ? v : 0;
+    for (int j = 0; j < a.steps; ++j) {
+        if (one_row_unit) load_dn<NX>(d, vv / F, a.ny, a.dn[vv % F] + j * plane);
+        grid_sync(a.counter, ++nbar, abort, a.status, a.limit);
+        for (int u = v; u < all_c; u += PAIR * G) {
+            const int u2 = u + G;
+            const bool two = PAIR == 2 && u2 < all_c;
+            const int f1 = u % F, f2 = u2 % F;
+            float2 va[kR], ha[kR], vb[kR], hb[kR];
+            col_load<NY>(u / F, a.nx, a.work[f1], a.H, va, ha);
+            if (two) col_load<NY>(u2 / F, a.nx, a.work[f2], a.H, vb, hb);
+            col_body<NY, false>(u / F, a.nx, a.work[f1], twy, smem, nullptr, nullptr, nullptr, va,
+                                ha);
+            if (two)
+                col_body<NY, false>(u2 / F, a.nx, a.work[f2], twy, smem, nullptr, nullptr,
+                                    nullptr, vb, hb);
+        }
+        grid_sync(a.counter, ++nbar, abort, a.status, a.limit);
+        for (int u = v; u < all_r; u += PAIR * G) {
+            const int u2 = u + G;
+            const bool two = PAIR == 2 && u2 < all_r;
+            const int f1 = u % F, r1 = u / F;
+            const int f2 = u2 % F, r2 = two ? u2 / F : 0;
+            float2 va[kR], vb[kR];
+            float db[kR];
+            row_load<NX, kSpecIn>(r1, a.ny, a.work[f1], va);
+            if (!one_row_unit) load_dn<NX>(d, r1, a.ny, a.dn[f1] + j * plane);
+            if (two) {
+                row_load<NX, kSpecIn>(r2, a.ny, a.work[f2], vb);
+                load_dn<NX>(db, r2, a.ny, a.dn[f2] + j * plane);
+            }
+            const RowArgs ra{a.work[f1], a.work[f1],
+                             a.inten[f1] ? a.inten[f1] + j * plane : nullptr, nullptr, nullptr,
+                             nullptr, nullptr, a.k0dz};
+            if (j + 1 < a.steps)
+                row_body<NX, kSpecIn, kScreen, kSpecOut>(r1, a.ny, ra, d, twx, smem, va);
+            else
+                row_body<NX, kSpecIn, kScreen, kNaturalOut>(r1, a.ny, ra, d, twx, smem, va);
+            if (two) {
+                const RowArgs rb{a.work[f2], a.work[f2],
+                                 a.inten[f2] ? a.inten[f2] + j * plane : nullptr, nullptr,
+                                 nullptr, nullptr, nullptr, a.k0dz};
+                if (j + 1 < a.steps)
+                    row_body<NX, kSpecIn, kScreen, kSpecOut>(r2, a.ny, rb, db, twx, smem, vb);
+                else
+                    row_body<NX, kSpecIn, kScreen, kNaturalOut>(r2, a.ny, rb, db, twx, smem, vb);
+            }
+        }
+    }
+}
+
+// ---------------------------------------------------------------------------
+// persistent adjoint march with checkpointing
+//
+//   1. forward march from u_0 keeping u at every K-th slice boundary;
+//   2. for each segment of K steps, last to first: recompute the segment's
+//      fields from its checkpoint (kept in one of two `seg` buffers), then
+//      run its adjoint steps backwards; the recompute of the segment before
+//      shares the passes of these adjoint steps; the adjoint state crosses
+//      segments in `gwork`;
+//   3. a tail row pass brings g_0 back to natural order.
+// Memory: ceil(N/K) + 2 K + 2 fields (K + 2 more than the checkpoints and
+// one segment); compute: about three forward marches in about two marches'
+// worth of passes.
+
+struct AdjointArgs {
+    const float2* field_in;
+    const float* dn;
+    const float2* gout;  // dL/du_N or null
+    const float* gI;     // dL/dI or null
+    float2* gin;         // dL/du_0 or null
+    float2* gspec;       // dL/dU_0 or null
+    float* gdn;          // dL/ddn or null
+    float2* fwork;
+    float2* gwork;
+    float2* ckpt;  // [ceil(N/K)] fields (slot 0 unused: u_0 is field_in)
+    float2* seg;   // [2 K] fields: two segment buffers
+    const float2* H;
+    const float2* twx;
+    const float2* twy;
+    const int* permx;
+    const int* permy;
+    unsigned* counter;
+    unsigned* status;
+    unsigned limit;
+    int nx, ny, steps, K;
+    float k0dz;
+};
+
+// BLK = threads per workgroup: 64 for fields of at most 512^2, so that a
+// small field still spreads over many CUs (a 256^2 field has 64 units of 4
+// rows instead of 16 of 16).
+template <int NX, int NY, int BLK>
+__global__ __launch_bounds__(BLK) void adjoint_kernel(AdjointArgs a) {
+    extern __shared__ float2 smem[];
+    const int G = gridDim.x, v = virtual_block();
+    const int rows_u = (a.ny + units_per_block<NX, BLK>() - 1) / units_per_block<NX, BLK>();
+    const int cols_u = (a.nx + units_per_block<NY, BLK>() - 1) / units_per_block<NY, BLK>();
+    const size_t plane = (size_t)a.nx * a.ny;
+    const int N = a.steps, K = a.K, C = (N + K - 1) / K;
+    unsigned nbar = 0;
+    bool abort = false;
+    Twiddles<NX, kR> twx;
+    Twiddles<NY, kR> twy;
+    twx.load(a.twx, threadIdx.x % (NX / kR));
+    twy.load(a.twy, threadIdx.x / units_per_block<NY, BLK>());
+    float d[kR];
+    for (int i = 0; i < kR; ++i) d[i] = 0.f;
+
+    auto col_pass = [&](float2* work, bool conj, float2* spec_out) {
+        for (int u = v; u < cols_u; u += G) {
+            if (conj)
+                col_unit<NY, true, BLK>(u, a.nx, work, a.H, twy, smem, spec_out, a.permx, a.permy);
+            else
+                col_unit<NY, false, BLK>(u, a.nx, work, a.H, twy, smem, nullptr, nullptr, nullptr);
+        }
+    };
+
+    // 1. checkpoints u_K, u_2K, ..., u_(C-1)K
+    if (C > 1) {
+        RowArgs ra{a.field_in, a.fwork, nullptr, nullptr, nullptr, nullptr, nullptr, a.k0dz};
+        for (int u = v; u < rows_u; u += G)
+            row_unit<NX, kNaturalIn, kNoOps, kSpecOut, BLK>(u, a.ny, ra, d, twx, smem);
+        ra.src = a.fwork;
+        const int last = (C - 1) * K;
+        for (int j = 0; j < last; ++j) {
+            grid_sync(a.counter, ++nbar, abort, a.status, a.limit);
+            col_pass(a.fwork, false, nullptr);
+            grid_sync(a.counter, ++nbar, abort, a.status, a.limit);
+            ra.keep = ((j + 1) % K == 0) ? a.ckpt + (size_t)((j + 1) / K) * plane : nullptr;
+            for (int u = v; u < rows_u; u += G) {
+                load_dn<NX, BLK>(d, u, a.ny, a.dn + j * plane);
+                if (j + 1 < last)
+                    row_unit<NX, kSpecIn, kScreen, kSpecOut, BLK>(u, a.ny, ra, d, twx, smem);
+                else
+                    row_unit<NX, kSpecIn, kScreen, kNoOut, BLK>(u, a.ny, ra, d, twx, smem);
+            }
+        }
+    }
+
+    // 2. segments, last to first.  Recomputing segment c from its checkpoint
+    // takes 2 L + 1 passes (the head row pass to the spectrum, then a column
+    // and a row pass per step, the row passes keeping u in segment buffer
+    // c % 2); its adjoint steps take 2 L passes (a row and a column pass per
+    // step, last step first) and read that buffer.  The recompute of segment
+    // c - 1 runs in the same passes as the adjoint steps of segment c (the
+    // other buffer, the other work field), so one grid barrier serves both.
+    auto seg_of = [&](int c) { return a.seg + (size_t)(c & 1) * K * plane; };
+    auto len_of = [&](int c) { return N - c * K < K ? N - c * K : K; };
+    // units of pass i: recompute: 0 head row, odd column, even row;
+    // adjoint: even row, odd column
+    auto rec_units = [&](int i) { return i % 2 == 0 ? rows_u : cols_u; };
+    auto adj_units = [&](int i) { return i % 2 == 0 ? rows_u : cols_u; };
+    auto rec_unit = [&](int c, int i, int u) {
+        if (i == 0) {
+            RowArgs fr{c == 0 ? a.field_in : a.ckpt + (size_t)c * plane, a.fwork, nullptr,
+                       nullptr, nullptr, nullptr, nullptr, a.k0dz};
+            row_unit<NX, kNaturalIn, kNoOps, kSpecOut, BLK>(u, a.ny, fr, d, twx, smem);
+        } else if (i % 2 == 1) {
+            col_unit<NY, false, BLK>(u, a.nx, a.fwork, a.H, twy, smem, nullptr, nullptr, nullptr);
+        } else {
+            const int t = i / 2 - 1;
+            RowArgs fr{a.fwork, a.fwork, nullptr, seg_of(c) + (size_t)t * plane, nullptr,
+                       nullptr, nullptr, a.k0dz};
+            load_dn<NX, BLK>(d, u, a.ny, a.dn + (size_t)(c * K + t) * plane);
+            if (t + 1 < len_of(c))
+                row_unit<NX, kSpecIn, kScreen, kSpecOut, BLK>(u, a.ny, fr, d, twx, smem);
+            else
+                row_unit<NX, kSpecIn, kScreen, kNoOut, BLK>(u, a.ny, fr, d, twx, smem);
+        }
+    };
+    auto adj_unit = [&](int c, int i, int u) {
+        const int s = len_of(c) - 1 - i / 2, j = c * K + s;
+        if (i % 2 == 0) {
+            RowArgs br{a.gwork, a.gwork, nullptr, nullptr, seg_of(c) + (size_t)s * plane,
+                       a.gI ? a.gI + (size_t)j * plane : nullptr,
+                       a.gdn ? a.gdn + (size_t)j * plane : nullptr, a.k0dz};
+            load_dn<NX, BLK>(d, u, a.ny, a.dn + (size_t)j * plane);
+            if (j + 1 < N) {
+                row_unit<NX, kSpecIn, kAdjointOps, kSpecOut, BLK>(u, a.ny, br, d, twx, smem);
+            } else if (a.gout) {
+                br.src = a.gout;
+                row_unit<NX, kNaturalIn, kAdjointOps, kSpecOut, BLK>(u, a.ny, br, d, twx, smem);
+            } else {
+                row_unit<NX, kZeroIn, kAdjointOps, kSpecOut, BLK>(u, a.ny, br, d, twx, smem);
+            }
+        } else {
+            col_unit<NY, true, BLK>(u, a.nx, a.gwork, a.H, twy, smem, j == 0 ? a.gspec : nullptr,
+                                    a.permx, a.permy);
+        }
+    };
+    // the last segment's recompute alone, then adjoint c with recompute c - 1
+    for (int i = 0; i < 2 * len_of(C - 1) + 1; ++i) {
+        grid_sync(a.counter, ++nbar, abort, a.status, a.limit);
+        for (int u = v; u < rec_units(i); u += G) rec_unit(C - 1, i, u);
+    }
+    for (int c = C - 1; c >= 0; --c) {
+        const int PA = 2 * len_of(c), PR = c > 0 ? 2 * len_of(c - 1) + 1 : 0;
+        for (int i = 0; i < (PA > PR ? PA : PR); ++i) {
+            grid_sync(a.counter, ++nbar, abort, a.status, a.limit);
+            const int na = i < PA ? adj_units(i) : 0, nr = i < PR ? rec_units(i) : 0;
+            for (int u = v; u < na + nr; u += G) {
+                if (u < na)
+                    adj_unit(c, i, u);
+                else
+                    rec_unit(c - 1, i, u - na);
+            }
+        }
+    }
+
+    // 3. g_0 in natural order
+    if (a.gin) {
+        grid_sync(a.counter, ++nbar, abort, a.status, a.limit);
+        RowArgs tr{a.gwork, a.gin, nullptr, nullptr, nullptr, nullptr, nullptr, a.k0dz};
+        for (int u = v; u < rows_u; u += G)
+            row_unit<NX, kSpecIn, kNoOps, kNaturalOut, BLK>(u, a.ny, tr, d, twx, smem);
+    }
+}
+
+// ---------------------------------------------------------------------------
+// launchers
+
+template <int NX, int NY, int BLK = kBlock>
+inline size_t persistent_lds() {
+    const size_t lds_r = sizeof(float2) * units_per_block<NX, BLK>() * lds_size<NX>();
+    const size_t lds_c = sizeof(float2) * units_per_block<NY, BLK>() * lds_size<NY>();
+    return lds_r > lds_c ? lds_r : lds_c;
+}
+
+template <int NX, int NY, int BLK = kBlock>
+inline int persistent_grid(int nx, int ny, int fields = 1, int per_cu = 1) {
+    const int rows_u = (ny + units_per_block<NX, BLK>() - 1) / units_per_block<NX, BLK>();
+    const int cols_u = (nx + units_per_block<NY, BLK>() - 1) / units_per_block<NY, BLK>();
+    const int cus = device_cus() * per_cu;
+    const int grid = (rows_u > cols_u ? rows_u : cols_u) * fields;
+    return grid > cus ? cus : grid;
+}
+
+// calls f(std::integral_constant<int, ny>{}) for a supported column length
+template <typename F>
+inline hipError_t dispatch_ny(int ny, F&& f) {
+    return dispatch_size(ny, f);
+}
+
+template <int NX>
+hipError_t launch_forward_x(const MarchArgs& a, hipStream_t s) {
+    return dispatch_ny(a.ny, [&](auto yc) {
+        constexpr int NY = decltype(yc)::value;
+        void* args[] = {const_cast<MarchArgs*>(&a)};
+        if constexpr (NX >= 512 && NY >= 512) {
+            if (a.fields >= 2)
+                return hipLaunchCooperativeKernel(
+                    reinterpret_cast<const void*>(&march_kernel<NX, NY, 2>),
+                    dim3(persistent_grid<NX, NY>(a.nx, a.ny, a.fields, 2)), dim3(kBlock), args,
+                    (unsigned)(march_data_lds<NX, NY>() + sizeof(float2) * (NX + NY)), s);
+        }
+        return hipLaunchCooperativeKernel(reinterpret_cast<const void*>(&march_kernel<NX, NY, 1>),
+                                          dim3(persistent_grid<NX, NY>(a.nx, a.ny, a.fields)),
+                                          dim3(kBlock), args, (unsigned)persistent_lds<NX, NY>(),
+                                          s);
+    });
+}
+
+template <int NX>
+hipError_t launch_adjoint_x(const AdjointArgs& a, hipStream_t s) {
+    return dispatch_ny(a.ny, [&](auto yc) {
+        constexpr int NY = decltype(yc)::value;
+        constexpr int BLK = NX <= 512 && NY <= 512 ? 64 : kBlock;
+        void* args[] = {const_cast<AdjointArgs*>(&a)};
+        return hipLaunchCooperativeKernel(
+            reinterpret_cast<const void*>(&adjoint_kernel<NX, NY, BLK>),
+            dim3(persistent_grid<NX, NY, BLK>(a.nx, a.ny, 2)), dim3(BLK), args,
+            (unsigned)persistent_lds<NX, NY, BLK>(), s);
+    });
+}
+
+// one translation unit per row length
+#define BPM_MARCH_INSTANTIATE(NX)                                                  \
+    template hipError_t launch_forward_x<NX>(const MarchArgs&, hipStream_t);      \
+    template hipError_t launch_adjoint_x<NX>(const AdjointArgs&, hipStream_t);
+#define BPM_MARCH_EXTERN(NX)                                                       \
+    extern template hipError_t launch_forward_x<NX>(const MarchArgs&, hipStream_t); \
+    extern template hipError_t launch_adjoint_x<NX>(const AdjointArgs&, hipStream_t);
+
+}  // namespace bpm

@@ -147,6 +147,13 @@ __device__ __forceinline__ void row_body(int unit, int ny, const RowArgs& a,
     const size_t rowoff = (size_t)(on ? row : 0) * NX;
     float2* lds = smem + sub * lds_size<NX>();
     const RowSync<NX> sync;
+    // A row of more than one wavefront: the previous unit's last LDS reads
+    // (by the other wavefronts of the row) may target the slots this unit's
+    // first exchange writes, whenever the two units enter or leave the
+    // transforms in different layouts (natural-order head or tail passes,
+    // mixed units of the adjoint).  Within one wavefront LDS operations stay
+    // in program order, so only multi-wavefront rows need this fence.
+    if constexpr (NX / kR > 64) __syncthreads();
     if constexpr (IN == kSpecIn) fft_inverse<NX, kR, 1>(v, lds, tau, twx, sync);
     if constexpr (OPS == kScreen) {
         float ph[kR];
@@ -272,9 +279,11 @@ __device__ __forceinline__ void col_unit(int unit, int nx, float2* work,
 // operations, so no L2 write-back or invalidation is needed.
 //
 // Every workgroup is resident (cooperative launch), so the wait ends; as a
-// guard against a launch that is not, the spin is bounded and a time-out is
-// recorded in the error word and ends all further waiting, so the kernel
-// always exits.
+// guard against a launch that is not, the spin is bounded (`limit` polls) and
+// a time-out is recorded, in the barrier's own word and in the workspace's
+// sticky status word (bit kStatusBarrier, never cleared by a kernel; the host
+// reads it through bpm_workspace_status), and ends all further waiting, so
+// the kernel always exits.
 //
 // Barrier words (unsigned, zeroed by the plan kernel before every march):
 //   [32 * g]        arrivals of group g        (g < 8)
@@ -282,9 +291,16 @@ __device__ __forceinline__ void col_unit(int unit, int nx, float2* work,
 //   [512]           closed groups
 //   [544]           time-out flag
 
-constexpr unsigned kSpinLimit = 1u << 22;
+// sticky status bits of a workspace's status header (word 0)
+constexpr unsigned kStatusBarrier = 1u;  // a grid-barrier wait gave up
+constexpr unsigned kStatusQueue = 2u;    // a work-queue dependency wait gave up
 
-__device__ __forceinline__ void grid_sync(unsigned* bar, unsigned gen, bool& abort) {
+__device__ __forceinline__ void record_timeout(unsigned* status, unsigned bit) {
+    __hip_atomic_fetch_or(status, bit, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+
+__device__ __forceinline__ void grid_sync(unsigned* bar, unsigned gen, bool& abort,
+                                          unsigned* status, unsigned limit) {
     __builtin_amdgcn_s_waitcnt(0);
     __syncthreads();
     if (threadIdx.x == 0) {
@@ -304,8 +320,9 @@ __device__ __forceinline__ void grid_sync(unsigned* bar, unsigned gen, bool& abo
         unsigned spins = 0;
         while (!abort && __hip_atomic_load(bar + 256 + 32 * g, __ATOMIC_RELAXED,
                                            __HIP_MEMORY_SCOPE_AGENT) < gen) {
-            if (++spins > kSpinLimit) {
+            if (++spins > limit) {
                 __hip_atomic_store(bar + 544, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+                record_timeout(status, kStatusBarrier);
                 abort = true;
             }
         }

@@ -87,20 +87,68 @@ def training_run(dn: torch.Tensor, depth: int, offset, pitch: int, scale: float,
     return patches, dep, bpm_psfs(dn, depth, src, scale, optics)
 
 
+def fallback_runs(yx, ny: int, nx: int, min_separation: int = CROP):
+    """Split sources ((y, x) pixels, host int array [n][2]) into multiplexed
+    runs in which every two sources lie more than ``min_separation`` pixels
+    apart along y or x (circularly): a stack then sees neighbours no closer
+    than in the training runs, whose sources sit on a grid of that pitch.
+
+    The plane is cut into square cells of side P (the power of two >=
+    min_separation, at most the field's side); cells are coloured by the
+    parity of their row and column index (a third colour for the last cell of
+    an odd count, which wraps onto cell 0), and the k-th source of a cell goes
+    to run (colour, k).  Two sources of one run are therefore in different
+    cells of one colour, at least one full cell apart.  Returns a list of
+    index arrays, one per run."""
+    import numpy as np
+    yx = np.asarray(yx, dtype=np.int64).reshape(-1, 2)
+    if len(yx) == 0:
+        return []
+
+    def axis(v, n):
+        P = 1
+        while P < min(max(min_separation, 1), n):
+            P *= 2
+        P = min(P, n)
+        c = (v % n) // P
+        nc = n // P
+        col = c % 2
+        if nc % 2 == 1 and nc > 1:
+            col = np.where(c == nc - 1, 2, col)
+        return c, col, nc
+
+    cy, coly, ncy = axis(yx[:, 0], ny)
+    cx, colx, ncx = axis(yx[:, 1], nx)
+    cell = cy * ncx + cx
+    order = np.argsort(cell, kind="stable")
+    rank = np.empty(len(yx), dtype=np.int64)
+    sc = cell[order]
+    start = np.r_[0, np.nonzero(np.diff(sc))[0] + 1]
+    first = np.repeat(start, np.diff(np.r_[start, len(sc)]))
+    rank[order] = np.arange(len(sc)) - first
+    key = (coly * 3 + colx) * (int(rank.max()) + 1) + rank
+    return [np.nonzero(key == k)[0] for k in np.unique(key)]
+
+
 def psf_with_fallback(weights: torch.Tensor, dn: torch.Tensor, sources: torch.Tensor,
-                      scale: float, threshold: float = 0.05, optics: Optics = Optics()):
+                      scale: float, threshold: float = 0.05, optics: Optics = Optics(),
+                      min_separation: int = CROP):
     """PSF stacks of point sources (int32 [n][3] = (z, y, x)) in a 64-slice
     volume: the surrogate's prediction, or the BPM stack where the predicted
     relative error exceeds ``threshold``.
 
     Returns (psf [n][32][32][32], pred_err [n], fallback mask [n] bool).  The
-    fallback runs one multiplexed march per distinct depth among the flagged
-    sources, so a replaced stack is bitwise the BPM readout of that run."""
+    flagged sources of each depth are split into runs (``fallback_runs``) so
+    that no two sources of one multiplexed march lie within
+    ``min_separation`` pixels of each other; a depth's runs march together,
+    up to eight in one lockstep launch, and each is read out on its own, so a
+    replaced stack is bitwise the BPM readout of its run."""
+    import numpy as np
     _need(dn, "dn", torch.float32)
     _need(sources, "sources", torch.int32)
     if sources.dim() != 2 or sources.shape[1] != 3:
         raise ValueError("sources must be [n][3] (z, y, x)")
-    nz = dn.shape[0]
+    nz, ny, nx = dn.shape
     if nz != _sg.PATCH[0]:
         raise ValueError(f"the surrogate's volumes have {_sg.PATCH[0]} slices, got {nz}")
     yx = sources[:, 1:].contiguous()
@@ -110,8 +158,34 @@ def psf_with_fallback(weights: torch.Tensor, dn: torch.Tensor, sources: torch.Te
     flagged = err > threshold
     idx = torch.nonzero(flagged).flatten()
     if idx.numel():
-        z = sources[idx, 0].cpu()
-        for d in torch.unique(z).tolist():
-            sel = idx[(z == d).to(idx.device)]
-            psf[sel] = bpm_psfs(dn, int(d), yx[sel].contiguous(), scale, optics)
+        src_h = sources[idx].cpu().numpy()
+        idx_h = idx.cpu().numpy()
+        for d in np.unique(src_h[:, 0]).tolist():
+            at = np.nonzero(src_h[:, 0] == d)[0]
+            runs = [at[r] for r in fallback_runs(src_h[at, 1:], ny, nx, min_separation)]
+            for b in range(0, len(runs), _MAX_LOCKSTEP):
+                group = runs[b:b + _MAX_LOCKSTEP]
+                sel = [torch.from_numpy(idx_h[r]).to(psf.device) for r in group]
+                stacks = _bpm_psfs_runs(dn, int(d), [yx[s_].contiguous() for s_ in sel], scale,
+                                        optics)
+                for s_, st in zip(sel, stacks):
+                    psf[s_] = st
     return psf, err, flagged
+
+
+_MAX_LOCKSTEP = 8   # fields of one geometry that march in one lockstep launch
+
+
+def _bpm_psfs_runs(dn: torch.Tensor, depth: int, runs, scale: float, optics: Optics):
+    """bpm_psfs of several runs at one depth, their marches in one batch call."""
+    nz, ny, nx = dn.shape
+    jobs = []
+    for src in runs:
+        u0 = _bpm.point_sources(src, nx, ny, optics.dx, optics.wavelength, optics.n0, optics.na,
+                                0.0)
+        jobs.append(dict(field=u0, dn=dn[depth:], dx=optics.dx, dz=optics.dz,
+                         wavelength=optics.wavelength, n0=optics.n0, out=u0, intensity=False))
+    exits = _bpm.propagate_batch(jobs)
+    return [_bpm.psf_readout(o, src, optics.dx, optics.dz, optics.wavelength, optics.n0,
+                             optics.na, nz - depth, planes=PLANES, crop=CROP, scale=scale)
+            for (o, _), src in zip(exits, runs)]

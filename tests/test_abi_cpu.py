@@ -217,3 +217,50 @@ def test_point_sources_validation(L):
                                None) == B.BPM_ERR_INVALID_ARG
     assert L.bpm_point_sources(b.p, None, 4, 64, 64, 0.2, 0.5, 1.33, 0.6, 0.0, b.p, b.p, 8,
                                None) == B.BPM_ERR_WORKSPACE
+
+
+def test_status_word_maps_to_device_error(L):
+    """The sticky mask that the persistent kernels set when a wait gives up
+    (word 0 of a workspace's status header) maps to BPM_ERR_DEVICE with a
+    message naming the kind of wait; a clear mask is BPM_OK."""
+    from paper_1706_02261_amd import _lib as B
+    assert L.bpm_decode_status(0) == B.BPM_OK
+    assert L.bpm_decode_status(1) == B.BPM_ERR_DEVICE
+    assert b"grid-barrier" in L.bpm_last_error() and b"not valid" in L.bpm_last_error()
+    assert L.bpm_decode_status(2) == B.BPM_ERR_DEVICE
+    assert b"work-queue" in L.bpm_last_error()
+    assert L.bpm_decode_status(3) == B.BPM_ERR_DEVICE
+    msg = L.bpm_last_error()
+    assert b"grid-barrier" in msg and b"work-queue" in msg
+    assert L.bpm_decode_status(0x80) == B.BPM_ERR_DEVICE
+    assert b"unknown" in L.bpm_last_error()
+
+
+def test_workspace_status_validation(L):
+    from paper_1706_02261_amd import _lib as B
+    b = Buf()
+    assert L.bpm_workspace_status(None, 4096, None) == B.BPM_ERR_WORKSPACE
+    assert L.bpm_workspace_status(b.p, 255, None) == B.BPM_ERR_WORKSPACE
+    assert L.bpm_workspace_status(b.p + 8, 4096, None) == B.BPM_ERR_WORKSPACE
+    assert L.bpm_set_wait_limit(1 << 40) == B.BPM_ERR_INVALID_ARG
+    assert L.bpm_set_wait_limit(0) == B.BPM_OK
+
+
+def test_fallback_runs_keep_sources_apart():
+    """Host grouping of the surrogate's fallback: every source in exactly one
+    run, and two sources of one run more than the crop pitch apart along y or
+    x, circularly (also across the wrap of the periodic field)."""
+    import itertools
+    from paper_1706_02261_amd.psfs import fallback_runs
+    rng = np.random.default_rng(5)
+    for n, m, sep in ((1024, 700, 32), (256, 200, 32), (64, 30, 32), (512, 300, 48)):
+        yx = rng.integers(0, n, (m, 2))
+        yx[:4] = [[0, 5], [n - 3, 5], [7, n - 1], [7, 2]]       # neighbours across the wrap
+        runs = fallback_runs(yx, n, n, sep)
+        assert sorted(np.concatenate(runs).tolist()) == list(range(m))
+        for r in runs:
+            for a, b in itertools.combinations(r, 2):
+                d = np.abs(yx[a] - yx[b])
+                d = np.minimum(d, n - d)
+                assert d.max() > sep
+    assert fallback_runs(np.zeros((0, 2), int), 64, 64) == []

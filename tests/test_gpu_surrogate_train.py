@@ -108,9 +108,11 @@ def test_fallback_is_the_bpm_readout(trained):
                                           threshold=-1.0)
     assert bool(fb.all())
     for d in (5, 40):
-        sel = torch.from_numpy(np.nonzero(src[:, 0] == d)[0]).cuda()
-        ref = psfs.bpm_psfs(vol, d, src_t[sel, 1:].contiguous(), trained["scale"])
-        assert torch.equal(psf[sel], ref)
+        at = np.nonzero(src[:, 0] == d)[0]
+        for run in psfs.fallback_runs(src[at, 1:], 1024, 1024):
+            sel = torch.from_numpy(at[run]).cuda()
+            ref = psfs.bpm_psfs(vol, d, src_t[sel, 1:].contiguous(), trained["scale"])
+            assert torch.equal(psf[sel], ref)
     psf2, err2, fb2 = psfs.psf_with_fallback(trained["blob"], vol, src_t, trained["scale"],
                                              threshold=float("inf"))
     pred, e = S.infer(trained["blob"], S.extract_patches(vol, src_t[:, 1:].contiguous()),
@@ -123,3 +125,20 @@ def test_fallback_is_the_bpm_readout(trained):
                                           threshold=thr)
     assert torch.equal(fb3, e > thr)
     assert torch.equal(psf3[~fb3], pred[~fb3])
+
+
+def test_fallback_never_multiplexes_neighbours(trained):
+    """Two flagged sources 5 px apart at one depth go to different runs: each
+    stack is bitwise the single-source BPM readout of that source, free of the
+    other's field."""
+    from paper_1706_02261_amd import psfs
+    vol = trained["val"][0]
+    src = torch.tensor([[20, 300, 300], [20, 305, 302]], dtype=torch.int32, device="cuda")
+    psf, _, fb = psfs.psf_with_fallback(trained["blob"], vol, src, trained["scale"],
+                                        threshold=-1.0)
+    assert bool(fb.all())
+    for i in range(2):
+        ref = psfs.bpm_psfs(vol, 20, src[i:i + 1, 1:].contiguous(), trained["scale"])
+        assert torch.equal(psf[i:i + 1], ref)
+    both = psfs.bpm_psfs(vol, 20, src[:, 1:].contiguous(), trained["scale"])
+    assert not torch.equal(both[0:1], psf[0:1])     # multiplexed together they would differ

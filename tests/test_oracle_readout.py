@@ -68,3 +68,35 @@ def test_modes_outside_the_na_are_cut():
     psf_out = oracle.psf_readout(outside, 0.2, 0.2, LAM, N0, NA, 0, [[0, 0]], planes=2, crop=8)
     assert np.abs(psf_in - 1).max() <= 1e-12
     assert np.abs(psf_out).max() <= 1e-24
+
+
+def test_refocus_planes_lie_downstream_of_the_source():
+    """Plane m of the readout is the field m dz past the source plane.
+
+    The source is a converging spectrum A(k) exp(-i kz q dz), written out
+    here: it focuses q dz downstream of its plane under the march's
+    propagator (whose sign the single-mode phase pin fixes).  Read out with
+    no back-propagation, its on-axis peak must sit at plane planes/2 + q, and
+    every plane m >= 1 must equal the free-space march of the source through
+    m slices; a readout that refocused upstream (the sign of m flipped) puts
+    the peak at planes/2 - q and fails both."""
+    n, dz, planes = 64, 0.2, 32
+    k0 = 2 * np.pi / LAM
+    f = np.fft.fftfreq(n, d=0.2) * 2 * np.pi
+    kx, ky = np.meshgrid(f, f)
+    kt2 = kx ** 2 + ky ** 2
+    kmax = k0 * NA
+    kz = np.sqrt(np.maximum((N0 * k0) ** 2 - kt2, 0.0))
+    amp = np.where(kt2 <= kmax ** 2, np.exp(-kt2 / kmax ** 2), 0.0)
+    for q in (5, -7):
+        u0 = np.fft.ifft2(amp * np.exp(-1j * kz * q * dz))
+        u0 = np.roll(u0, (n // 2, n // 2), axis=(0, 1))      # source at the grid centre
+        psf = oracle.psf_readout(u0, 0.2, dz, LAM, N0, NA, 0, [[n // 2, n // 2]],
+                                 planes=planes, crop=32)[0]
+        axis = psf[:, 16, 16]
+        assert int(np.argmax(axis)) == planes // 2 + q
+        steps = planes // 2 - 1
+        _, inten = oracle.bpm_forward(u0, np.zeros((steps, n, n)), 0.2, dz, LAM, N0)
+        for m in range(1, steps + 1):
+            ref = inten[m - 1][n // 2 - 16:n // 2 + 16, n // 2 - 16:n // 2 + 16]
+            assert np.abs(psf[planes // 2 + m] - ref).max() <= 1e-12 * ref.max()
