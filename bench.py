@@ -45,7 +45,7 @@ PAPER_GVS = 1024 ** 3 / 0.5 / 1e9  # < 500 ms for 1024^3 voxels, main text
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "march_1024cube_traffic.json")
 
 
-MARCH_SOURCES = ("fft.hpp", "mathx.hpp", "passes.hpp", "march.hip")
+MARCH_SOURCES = ("fft.hpp", "mathx.hpp", "passes.hpp", "march_kernels.hpp", "march_x1024.hip")
 
 
 def kernel_source_hash() -> str:
@@ -71,7 +71,37 @@ def measured_traffic():
     return t.get("bytes_per_launch")
 
 
-def cpu_baseline(u0, dn_host, g, gpu_fn, target_s=15.0):
+def cpu_model() -> str:
+    try:
+        with open("/proc/cpuinfo") as f:
+            for ln in f:
+                if ln.startswith("model name"):
+                    return ln.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    import platform
+    return platform.processor() or "unknown"
+
+
+def _oracle_gvs(u0, dn, g, reps=1):
+    """Median Gvoxel-steps/s of the oracle march (intensity volume included)
+    over `reps` runs after one warm-up when reps > 1; seconds of one run."""
+    import numpy as np
+    import oracle
+    ts = []
+    for _ in range(reps + (1 if reps > 1 else 0)):
+        t0 = time.perf_counter()
+        oracle.bpm_forward(u0, dn, g.dx, g.dz, g.wavelength, g.n0)
+        ts.append(time.perf_counter() - t0)
+    t = float(np.median(ts[1:] if reps > 1 else ts))
+    return g.nx * g.ny * dn.shape[0] / t / 1e9, t
+
+
+def cpu_baseline(u0, dn_host, g, gpu_fn, small, target_s=8.0):
+    """The FP64 oracle on the host cores: the paper-scale volume's first slices
+    (the bounded sample of the timed workload, with the GPU's error on it),
+    the same on one thread, and the 128^2 x 64 and 512^2 x 512 workloads in
+    full (the latter on one thread over its first 32 slices)."""
     import numpy as np
     import oracle
     threads = oracle.set_threads(0)
@@ -86,26 +116,86 @@ def cpu_baseline(u0, dn_host, g, gpu_fn, target_s=15.0):
     t = time.perf_counter() - t0
     got = gpu_fn(steps)
     err = float(np.linalg.norm(got - ref) / np.linalg.norm(ref))
+    workloads = {}
+    for name, (gs, us, ds), reps in ((k, v, 3 if k.startswith("128") else 1)
+                                     for k, v in small.items()):
+        gvs_n, t_n = _oracle_gvs(us, ds, gs, reps)
+        workloads[name] = {"gvoxel_steps_per_s": round(gvs_n, 4), "seconds": round(t_n, 3),
+                           "threads": threads}
+    try:
+        oracle.set_threads(1)
+        one = {}
+        one_steps = 4
+        t0 = time.perf_counter()
+        oracle.bpm_forward(u0, dn_host[:one_steps], g.dx, g.dz, g.wavelength, g.n0,
+                           intensity=False)
+        one["paper_scale_first_4_slices"] = round(g.nx * g.ny * one_steps /
+                                                  (time.perf_counter() - t0) / 1e9, 5)
+        for name, (gs, us, ds), in small.items():
+            cut = ds if name.startswith("128") else ds[:32]
+            gvs_1, _ = _oracle_gvs(us, cut, gs, 3 if name.startswith("128") else 1)
+            one[name if cut is ds else f"{name}_first_32_slices"] = round(gvs_1, 5)
+    finally:
+        oracle.set_threads(threads)
     return {"value": round(g.nx * g.ny * steps / t / 1e9, 4), "unit": "Gvoxel-steps/s",
             "cores": threads, "kind": "oracle",
             "sample": f"{g.nx}x{g.ny} field, first {steps} of {g.steps} slices of the timed "
                       f"volume, FP64 radix-2 oracle, OpenMP {threads} threads, "
                       f"{t:.1f} s",
+            "cpu_model": cpu_model(), "logical_cpus": os.cpu_count(),
+            "one_thread_gvoxel_steps_per_s": one, "workloads": workloads,
             "gpu_rel_l2_err_on_sample": err}
 
 
-SURROGATE_FLOP_PER_PSF = 2 * (8192 * 32 * 216 + 4096 * 32 * 864 + 2048 * 32 * 864
-                              + 1024 * 32 * 864 + 256 * 64 * 1152 + 1024 * 32 * 576)
+def workload_rates(dev, small, reps=10):
+    """The GPU march on the 128^2 x 64 (latency) and 512^2 x 512 workloads
+    (bpm_propagate, intensity volume written), median of `reps` launches."""
+    import numpy as np
+    import torch
+    import paper_1706_02261_amd as bpm
+    stream = torch.cuda.current_stream(dev)
+    out = {}
+    for name, (g, u0, dn) in small.items():
+        f = torch.from_numpy(u0).to(dev)
+        d = torch.from_numpy(dn).to(dev)
+        o = torch.empty_like(f)
+        inten = torch.empty(dn.shape, dtype=torch.float32, device=dev)
+        ws = bpm.workspace(bpm.workspace_size(g.nx, g.ny, g.steps), dev)
+
+        def run():
+            bpm.propagate(f, d, g.dx, g.dz, g.wavelength, g.n0, out=o, intensity_out=inten,
+                          ws=ws, stream=stream)
+
+        for _ in range(2):
+            run()
+        ts = []
+        for _ in range(reps):
+            a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            a.record(stream)
+            run()
+            b.record(stream)
+            torch.cuda.synchronize(dev)
+            ts.append(a.elapsed_time(b))
+        ms = float(np.median(ts))
+        vs = g.nx * g.ny * g.steps
+        gbs = BYTES_PER_VOXEL_STEP * vs / (ms / 1e3) / 1e9
+        out[name] = {"ms": round(ms, 4), "gvoxel_steps_per_s": round(vs / (ms / 1e3) / 1e9, 3),
+                     "hbm_frac_40B": round(gbs / HBM_PEAK_GBS, 4)}
+    return out
+
+
+SURROGATE_FLOP_PER_PSF = 2 * (8192 * 32 * 27 * 5 + 4096 * 32 * 27 * 32 + 2048 * 32 * 27 * 32
+                              + 1024 * 32 * 27 * 32 + 256 * 64 * 36 * 32 + 1024 * 32 * 9 * 64)
 MFMA_BF16_PEAK_TFLOPS = 2500.0
 
 
-def psf_rates(dev, n_runs=8, n_infer=100000, train_seconds=30.0):
+def psf_rates(dev, n_runs=8, n_infer=100000, train_seconds=60.0):
     """The learned PSF surrogate against the BPM on the same GPU.
 
     * BPM PSFs/s: multiplexed runs (1024 sources each, depths spread over the
       64-slice volume; point sources + march + readout);
-    * the surrogate is trained for `train_seconds` on BPM PSFs of two volumes
-      (16 runs, 16384 PSFs) and evaluated on 2048 held-out PSFs of a third:
+    * the surrogate is trained for `train_seconds` on 10^5 BPM PSFs of four
+      volumes (98 runs) and evaluated on 2048 held-out PSFs of a third:
       relative L2 error against the BPM, the error of the spatially invariant
       clear-medium PSF, the fraction above the 5 % fallback threshold;
     * surrogate PSFs/s on `n_infer` random sources of a fourth volume (patch
@@ -127,10 +217,17 @@ def psf_rates(dev, n_runs=8, n_infer=100000, train_seconds=30.0):
                for _ in range(n)]
         return [torch.cat([o[k] for o in out]) for k in range(3)]
 
-    train = [runs(torch.from_numpy(synth.surrogate_volume(c)).to(dev), 8) for c in (0, 1)]
+    # the training set: 10^5 BPM PSFs (98 multiplexed runs of 1024 sources
+    # over four volumes), as the learned part's workload states
+    t_gen = time.perf_counter()
+    train = [runs(torch.from_numpy(synth.surrogate_volume(c)).to(dev), n)
+             for c, n in ((0, 25), (1, 25), (4, 24), (5, 24))]
     X, D, T = (torch.cat([t[k] for t in train]) for k in range(3))
     del train
+    torch.cuda.synchronize(dev)
+    t_gen = time.perf_counter() - t_gen
     Xv, Dv, Tv = runs(torch.from_numpy(synth.surrogate_volume(2)).to(dev), 2)
+    n_train = int(X.shape[0])
     model = S.PSFSurrogate(dev, S.init_params(seed=0))
     epochs = model.fit(X, D, T, seconds=train_seconds)
     del X, D, T
@@ -143,6 +240,11 @@ def psf_rates(dev, n_runs=8, n_infer=100000, train_seconds=30.0):
     r_inv = rel(clear.expand_as(Tv), Tv)
     q = lambda v, p: round(float(torch.quantile(v.float().cpu(), p)), 4)
     corr = float(np.corrcoef(err.cpu().numpy(), r_s.cpu().numpy())[0, 1])
+    # of the held-out PSFs the error head accepts (predicted <= 5 %), the share
+    # whose true error against the BPM exceeds 5 %
+    acc = err <= 0.05
+    accepted_bad = (round(float((r_s[acc] > 0.05).float().mean()), 4) if bool(acc.any())
+                    else None)
     del Xv, Dv, Tv, pred
 
     vol = torch.from_numpy(synth.surrogate_volume(3)).to(dev)
@@ -189,12 +291,14 @@ def psf_rates(dev, n_runs=8, n_infer=100000, train_seconds=30.0):
         "surrogate_vs_bpm": round((n_infer / t_s) / (n_bpm / t_bpm), 4),
         "effective_psfs_per_s": round(n_infer / t_eff, 1),
         "fallback_rate": round(fb_rate, 4),
-        "training": {"psfs": 16384, "seconds": train_seconds, "epochs": epochs},
+        "training": {"psfs": n_train, "seconds": train_seconds, "epochs": epochs,
+                     "set_generation_s": round(t_gen, 1)},
         "heldout": {"psfs": 2048, "rel_err_median": q(r_s, 0.5), "rel_err_p95": q(r_s, 0.95),
                     "invariant_psf_rel_err_median": q(r_inv, 0.5),
                     "invariant_psf_rel_err_p95": q(r_inv, 0.95),
                     "error_head_corr": round(corr, 3),
-                    "above_5pct": round(float((err > 0.05).float().mean()), 4)},
+                    "above_5pct": round(float((err > 0.05).float().mean()), 4),
+                    "accepted_true_above_5pct": accepted_bad},
         "surrogate_roofline": {"bound": "mfma", "achieved": round(tflops, 2),
                                "peak": MFMA_BF16_PEAK_TFLOPS, "unit": "TFLOP/s",
                                "frac": round(tflops / MFMA_BF16_PEAK_TFLOPS, 5),
@@ -248,10 +352,12 @@ def adjoint_rate(dev, reps=3):
                          "bytes_per_voxel_step": ADJOINT_BYTES_PER_VOXEL_STEP}}
 
 
-def batch_rate(dev):
+def batch_rate(dev, replays=3):
     """The uneven batch: 64 jobs, nx, ny in {256, 512, 1024}, 128-1024 steps,
-    dn + intensity <= 160 GiB, one work-queue launch.  dn is uniform random in
-    [0, 0.05] drawn on the device (the rate does not depend on its values)."""
+    dn + intensity <= 160 GiB, one work-queue launch, timed as a replay of the
+    captured device half (bpm_batch_launch in a HIP graph, the configuration
+    asked for) and as a plain bpm_propagate_batch call.  dn is uniform random
+    in [0, 0.05] drawn on the device (the rate does not depend on its values)."""
     import numpy as np
     import torch
     import synth
@@ -267,33 +373,65 @@ def batch_rate(dev):
                          out=torch.empty_like(u0),
                          intensity_out=torch.empty((steps, ny, nx), dtype=torch.float32,
                                                    device=dev)))
-    arr = (B._lib.Job * len(jobs))(*[B._lib.Job(j["field"].data_ptr(), j["dn"].data_ptr(),
-                                                j["field"].shape[1], j["field"].shape[0],
-                                                j["dn"].shape[0], 0.2, 0.2, 0.5, 1.33,
-                                                j["out"].data_ptr(),
-                                                j["intensity_out"].data_ptr())
-                                     for j in jobs])
-    ws = B.workspace(B.lib().bpm_batch_workspace_size(arr, len(jobs)), dev)
+    ws = B.workspace(B._batch_table(jobs)[2], dev)
     stream = torch.cuda.current_stream(dev)
+    ev = lambda: (torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True))
     bpm.propagate_batch(jobs, ws=ws, stream=stream)
     torch.cuda.synchronize(dev)
-    a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    a, b = ev()
     a.record(stream)
     bpm.propagate_batch(jobs, ws=ws, stream=stream)
     b.record(stream)
     torch.cuda.synchronize(dev)
-    ms = a.elapsed_time(b)
+    ms_call = a.elapsed_time(b)
+    ref = [j["out"].clone() for j in jobs]
+    del ws
+    prep = B.PreparedBatch(jobs)
+    torch.cuda.synchronize(dev)
+    graph = torch.cuda.CUDAGraph()
+    with torch.cuda.graph(graph):
+        prep.launch()
+    graph.replay()
+    torch.cuda.synchronize(dev)
+    ts = []
+    for _ in range(replays):
+        a, b = ev()
+        a.record(stream)
+        graph.replay()
+        b.record(stream)
+        torch.cuda.synchronize(dev)
+        ts.append(a.elapsed_time(b))
+    same = all(torch.equal(j["out"], r) for j, r in zip(jobs, ref))
+    ms = float(np.median(ts))
     vs = sum(nx * ny * st for nx, ny, st in specs)
     achieved = BYTES_PER_VOXEL_STEP * vs / (ms / 1e3) / 1e9
-    del jobs, ws
+    del jobs, prep, graph, ref
     torch.cuda.empty_cache()
     return {"workload": f"{len(specs)} uneven jobs (nx, ny in 256..1024, steps 128..1024), "
-                        "one persistent work-queue launch",
-            "voxel_steps": vs, "ms": round(ms, 2),
+                        "one persistent work-queue launch, replayed from a captured graph",
+            "voxel_steps": vs, "ms": round(ms, 2), "ms_uncaptured_call": round(ms_call, 2),
+            "replay_fields_equal_call": same,
             "gvoxel_steps_per_s": round(vs / (ms / 1e3) / 1e9, 3),
             "roofline": {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,
                          "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),
                          "bytes_per_voxel_step": BYTES_PER_VOXEL_STEP}}
+
+
+def phase_split(jobs, ws, stream, launch_ms):
+    """One run of the timed launch with per-workgroup phase timers: mean and
+    max over workgroups of each phase, in microseconds per step."""
+    import torch
+    from paper_1706_02261_amd import bpm as B
+    _, t = B.march_phase_times(jobs, ws=ws, stream=stream)
+    torch.cuda.synchronize()
+    steps = t["steps"]
+    out = {"workgroups": t["workgroups"], "fields": t["fields"], "steps": steps,
+           "unit": "us per step (mean over workgroups / max)",
+           "launch_us_per_step": round(launch_ms * 1e3 / steps, 3)}
+    for name in B.PHASES:
+        v = t[name] * 1e6 / steps
+        out[name] = [round(float(v.mean()), 3), round(float(v.max()), 3)]
+    return out
 
 
 def main():
@@ -304,12 +442,16 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--slices", type=int, default=1024, help="march depth (default 1024)")
     ap.add_argument("--no-psf", action="store_true", help="skip the surrogate vs BPM PSF rates")
-    ap.add_argument("--train-seconds", type=float, default=30.0,
-                    help="surrogate training time of the PSF block (default 30)")
+    ap.add_argument("--train-seconds", type=float, default=60.0,
+                    help="surrogate training time of the PSF block (default 60)")
     ap.add_argument("--psf-only", action="store_true",
                     help="only the surrogate vs BPM PSF rates (for profiling those kernels)")
     ap.add_argument("--no-extra", action="store_true",
                     help="skip the adjoint and uneven-batch rates")
+    ap.add_argument("--phase-times", action="store_true",
+                    help="also run the timed launch once with per-workgroup phase timers and "
+                         "report the split of a step into pass work, store drain and barrier "
+                         "waits")
     ap.add_argument("--copy-mib", type=int, default=0,
                     help="also run a plain device copy of this many MiB (the known-size "
                          "kernel that scales rocprofv3's FETCH_SIZE / WRITE_SIZE counters)")
@@ -419,6 +561,8 @@ def main():
         },
         "input_generation_s": round(t_gen, 1),
     }
+    if args.phase_times:
+        line["phase_split"] = phase_split(jobs, ws, stream, launch_ms)
     if args.copy_mib:
         src = torch.ones(args.copy_mib * 2 ** 18, dtype=torch.float32, device=dev)
         dst = torch.empty_like(src)
@@ -427,7 +571,11 @@ def main():
         line["copy_calibration_bytes"] = src.numel() * 4
     if not args.no_psf:
         line["psf"] = psf_rates(dev, train_seconds=args.train_seconds)
+    small = None
+    if not (args.no_extra and args.no_cpu_baseline):
+        small = {"128x128x64": synth.config0(), "512x512x512": synth.config1()}
     if not args.no_extra:
+        line["workloads"] = workload_rates(dev, small)
         line["adjoint"] = adjoint_rate(dev)
         line["uneven_batch"] = batch_rate(dev)
     if not args.no_cpu_baseline:
@@ -438,7 +586,7 @@ def main():
             (o, _), _ = bpm.propagate_batch(part)
             torch.cuda.synchronize(dev)
             return o.cpu().numpy()
-        line["cpu_baseline"] = cpu_baseline(u0, dn_host, g, gpu_first)
+        line["cpu_baseline"] = cpu_baseline(u0, dn_host, g, gpu_first, small)
     print(json.dumps(line), flush=True)
 
 

@@ -146,6 +146,20 @@ int bpm_batch_upload(const bpm_job* jobs, int n_jobs,
 int bpm_batch_launch(const bpm_job* jobs, int n_jobs,
                      void* workspace, size_t workspace_bytes, void* hip_stream);
 
+/* Diagnostic: the lockstep march of bpm_propagate_batch (1 to 8 jobs of one
+ * geometry, steps >= 1; other batches return BPM_ERR_INVALID_ARG) with
+ * per-workgroup phase timers.  Results are those of bpm_propagate_batch.
+ * timers: device buffer of at least BPM_PHASE_TIMER_WORDS 64-bit words,
+ * 8-byte aligned; the call zeroes it, then writes words 0..3 = {workgroups,
+ * counter ticks per second, steps, fields} and, for workgroup w, 8 words at
+ * 8 (w + 1): ticks spent in {set-up, head pass, column passes, row passes,
+ * draining stores before grid barriers, waiting at grid barriers, 0, 0}.
+ * Workspace as for bpm_propagate_batch. */
+#define BPM_PHASE_TIMER_WORDS (8 + 8 * 4096)
+int bpm_march_phase_times(const bpm_job* jobs, int n_jobs, void* workspace,
+                          size_t workspace_bytes, unsigned long long* timers,
+                          size_t timer_bytes, void* hip_stream);
+
 /* Bytes of workspace for bpm_adjoint with an explicit checkpoint interval
  * (0 selects ceil(sqrt(steps))). */
 size_t bpm_adjoint_workspace_size(int nx, int ny, int steps, int checkpoint_every);

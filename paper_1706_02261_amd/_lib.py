@@ -36,7 +36,9 @@ EXPORTS = (
     "psf_surrogate_layer_geometry", "psf_extract_patches",
     "bpm_point_sources_workspace_size", "bpm_point_sources",
     "bpm_workspace_status", "bpm_decode_status", "bpm_set_wait_limit",
+    "bpm_march_phase_times",
 )
+PHASE_TIMER_WORDS = 8 + 8 * 4096
 
 
 class BpmError(RuntimeError):
@@ -118,6 +120,8 @@ def _declare(L):
     L.bpm_psf_readout.argtypes = [_V, _I, _I, _D, _D, _D, _D, _D, _I, _V, _I, _I, _I, _D, _V,
                                   _V, _Z, _V]
     L.bpm_psf_readout.restype = _I
+    L.bpm_march_phase_times.argtypes = [ctypes.POINTER(Job), _I, _V, _Z, _V, _Z, _V]
+    L.bpm_march_phase_times.restype = _I
     L.bpm_workspace_status.argtypes = [_V, _Z, _V]
     L.bpm_workspace_status.restype = _I
     L.bpm_decode_status.argtypes = [ctypes.c_uint]

@@ -278,6 +278,30 @@ def propagate_batch(jobs, ws: torch.Tensor | None = None, stream=None):
     return results
 
 
+PHASES = ("setup", "head", "column", "row", "drain", "wait")
+
+
+def march_phase_times(jobs, ws: torch.Tensor | None = None, stream=None):
+    """The lockstep march of ``propagate_batch`` (1-8 jobs of one geometry)
+    with per-workgroup phase timers.  Returns (results, times) where times is a
+    dict: "workgroups", "steps", "fields" and, per phase name in PHASES, a
+    float64 tensor [workgroups] of seconds."""
+    arr, results, need, dev = _batch_table(jobs)
+    if ws is None:
+        ws = workspace(need, dev)
+    t = torch.empty(_lib.PHASE_TIMER_WORDS, dtype=torch.int64, device=dev)
+    rc = lib().bpm_march_phase_times(arr, len(jobs), _ptr(ws), ws.numel(), _ptr(t),
+                                     t.numel() * 8, _stream_ptr(stream))
+    check(rc, "bpm_march_phase_times")
+    h = t.cpu()
+    G, rate, steps, fields = (int(h[k]) for k in range(4))
+    rec = h[8:8 + 8 * G].view(G, 8).double() / rate
+    times = {"workgroups": G, "steps": steps, "fields": fields}
+    for k, name in enumerate(PHASES):
+        times[name] = rec[:, k]
+    return results, times
+
+
 class PreparedBatch:
     """An uneven batch whose tables sit in its own workspace, so that
     ``launch()`` issues device work only and can be captured into a graph

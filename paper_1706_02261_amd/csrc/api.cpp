@@ -392,6 +392,38 @@ int bpm_propagate_batch(const bpm_job* jobs, int n_jobs, void* workspace,
     return batch_device(jobs, n_jobs, ws, L, s);
 }
 
+int bpm_march_phase_times(const bpm_job* jobs, int n_jobs, void* workspace,
+                          size_t workspace_bytes, unsigned long long* timers, size_t timer_bytes,
+                          void* hip_stream) {
+    int rc = check_batch(jobs, n_jobs);
+    if (rc) return rc;
+    if (n_jobs > bpm::kMaxFields || jobs[0].steps < 1)
+        return fail(BPM_ERR_INVALID_ARG, "phase times need 1..%d jobs with steps >= 1",
+                    bpm::kMaxFields);
+    for (int i = 1; i < n_jobs; ++i)
+        if (jobs[i].nx != jobs[0].nx || jobs[i].ny != jobs[0].ny ||
+            jobs[i].steps != jobs[0].steps || jobs[i].dx != jobs[0].dx ||
+            jobs[i].dz != jobs[0].dz || jobs[i].wavelength != jobs[0].wavelength ||
+            jobs[i].n0 != jobs[0].n0)
+            return fail(BPM_ERR_INVALID_ARG, "phase times need jobs of one geometry (job %d)", i);
+    if (!timers || !aligned(timers, 8) || timer_bytes < sizeof(unsigned long long) *
+                                                          bpm::kPhaseTimerWords)
+        return fail(BPM_ERR_INVALID_ARG, "timers must be 8-byte aligned, >= %zu bytes",
+                    sizeof(unsigned long long) * bpm::kPhaseTimerWords);
+    const BatchLayout L = batch_layout(jobs, n_jobs);
+    if ((rc = check_workspace(workspace, workspace_bytes, L.total))) return rc;
+    hipStream_t s = static_cast<hipStream_t>(hip_stream);
+    const bpm_job& j0 = jobs[0];
+    const bpm::Geom g{j0.nx, j0.ny, j0.steps, j0.dx, j0.dz, j0.wavelength, j0.n0};
+    const bpm::Plan p = bpm::plan_carve(static_cast<char*>(workspace) + L.plan_off[0], j0.nx, j0.ny);
+    if ((rc = device_status(bpm::launch_plan(g, p, true, s), "plan"))) return rc;
+    if ((rc = device_status(hipMemsetAsync(timers, 0, timer_bytes, s), "timers"))) return rc;
+    bpm::MarchIO io[bpm::kMaxFields];
+    for (int i = 0; i < n_jobs; ++i)
+        io[i] = bpm::MarchIO{jobs[i].field_in, jobs[i].dn, jobs[i].field_out, jobs[i].intensity_out};
+    return device_status(bpm::launch_forward(g, p, io, n_jobs, s, timers), "timed march");
+}
+
 int bpm_batch_upload(const bpm_job* jobs, int n_jobs, void* workspace, size_t workspace_bytes,
                      void* hip_stream) {
     int rc = check_batch(jobs, n_jobs);

@@ -54,8 +54,11 @@ struct MarchIO {
     void* field_out;       // float2 [ny][nx]
     float* intensity;      // [steps][ny][nx] or nullptr
 };
+// timers: per-workgroup phase timers (diagnostic, see PhaseTimers) or null
 hipError_t launch_forward(const Geom& g, const Plan& p, const MarchIO* io, int fields,
-                          hipStream_t s);
+                          hipStream_t s, unsigned long long* timers = nullptr);
+// words of the phase-timer buffer: a header and one record per workgroup
+constexpr size_t kPhaseTimerWords = 8 + 8 * 4096;
 
 // Adjoint march (steps >= 1) with a checkpoint every K steps; `fields` holds
 // adjoint_fields(steps, K) fields of nx * ny complex64.

@@ -273,7 +273,7 @@ static hipError_t dispatch_nx(int nx, F&& f) {
 }
 
 hipError_t launch_forward(const Geom& g, const Plan& p, const MarchIO* io, int fields,
-                          hipStream_t s) {
+                          hipStream_t s, unsigned long long* timers) {
     const size_t plane = (size_t)g.nx * g.ny;
     if (fields < 1 || fields > kMaxFields) return hipErrorInvalidValue;
     if (g.steps == 0) {
@@ -299,6 +299,7 @@ hipError_t launch_forward(const Geom& g, const Plan& p, const MarchIO* io, int f
     a.counter = (unsigned*)p.counter;
     a.status = (unsigned*)p.status;
     a.limit = wait_limit();
+    a.timers = timers;
     a.nx = g.nx;
     a.ny = g.ny;
     a.steps = g.steps;

@@ -39,6 +39,7 @@ struct MarchArgs {
     unsigned* counter;
     unsigned* status;  // the workspace's sticky status word
     unsigned limit;    // polls of one barrier wait before it gives up
+    unsigned long long* timers;  // phase timers (diagnostic) or null
     int nx, ny, steps, fields;
     float k0dz;
 };
@@ -51,10 +52,13 @@ struct MarchArgs {
 template <int NX, int NY, int OCC>
 __global__ __launch_bounds__(kBlock, OCC) void march_kernel(MarchArgs a) {
     extern __shared__ float2 smem[];
+    PhaseTimers tm;
+    tm.start(a.timers);
     const int G = gridDim.x, v = virtual_block();
     const int rows_u = (a.ny + units_per_block<NX>() - 1) / units_per_block<NX>();
     const int cols_u = (a.nx + units_per_block<NY>() - 1) / units_per_block<NY>();
     const int all_r = rows_u * a.fields, all_c = cols_u * a.fields;
+    PhaseTimers* tp = a.timers ? &tm : nullptr;
     const size_t plane = (size_t)a.nx * a.ny;
     unsigned nbar = 0;
     bool abort = false;
@@ -81,17 +85,20 @@ __global__ __launch_bounds__(kBlock, OCC) void march_kernel(MarchArgs a) {
     // units of one column range sit next to each other, so the workgroups of
     // an XCD share that range's slice of the propagator table in its L2
     const int F = a.fields;
+    tm.mark(kPhSetup);
     for (int u = v; u < all_r; u += G) {
         const int f = u % F;
         RowArgs ra{a.field_in[f], a.work[f], nullptr, nullptr, nullptr, nullptr, nullptr, a.k0dz};
         row_unit<NX, kNaturalIn, kNoOps, kSpecOut>(u / F, a.ny, ra, d, twx, smem);
     }
+    tm.mark(kPhHead);
     // a workgroup with a single row unit fetches its dn slice during the column pass
     const bool one_row_unit = all_r <= G;
     const int vv = v < all_r ? v : 0;
     for (int j = 0; j < a.steps; ++j) {
         if (one_row_unit) load_dn<NX>(d, vv / F, a.ny, a.dn[vv % F] + j * plane);
-        grid_sync(a.counter, ++nbar, abort, a.status, a.limit);
+        tm.mark(kPhRow);
+        grid_sync(a.counter, ++nbar, abort, a.status, a.limit, tp);
         for (int u = v; u < all_c; u += PAIR * G) {
             const int u2 = u + G;
             const bool two = PAIR == 2 && u2 < all_c;
@@ -105,7 +112,8 @@ __global__ __launch_bounds__(kBlock, OCC) void march_kernel(MarchArgs a) {
                 col_body<NY, false>(u2 / F, a.nx, a.work[f2], twy, smem, nullptr, nullptr,
                                     nullptr, vb, hb);
         }
-        grid_sync(a.counter, ++nbar, abort, a.status, a.limit);
+        tm.mark(kPhCol);
+        grid_sync(a.counter, ++nbar, abort, a.status, a.limit, tp);
         for (int u = v; u < all_r; u += PAIR * G) {
             const int u2 = u + G;
             const bool two = PAIR == 2 && u2 < all_r;
@@ -137,6 +145,9 @@ __global__ __launch_bounds__(kBlock, OCC) void march_kernel(MarchArgs a) {
             }
         }
     }
+    __builtin_amdgcn_s_waitcnt(0);
+    tm.mark(kPhRow);
+    tm.finish(v, a.steps, a.fields);
 }
 
 // ---------------------------------------------------------------------------
@@ -363,6 +374,8 @@ hipError_t launch_adjoint_x(const AdjointArgs& a, hipStream_t s) {
             (unsigned)persistent_lds<NX, NY, BLK>(), s);
     });
 }
+
+static_assert(kPhaseTimerWords == kPhaseWords * (kMaxTimedGroups + 1), "timer layout");
 
 // one translation unit per row length
 #define BPM_MARCH_INSTANTIATE(NX)                                                  \

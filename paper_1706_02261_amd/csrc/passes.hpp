@@ -299,10 +299,49 @@ __device__ __forceinline__ void record_timeout(unsigned* status, unsigned bit) {
     __hip_atomic_fetch_or(status, bit, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
 }
 
+// Per-workgroup phase timers of the persistent marches (a diagnostic, off
+// unless the launch passes a buffer): the device's constant 100 MHz real-time
+// counter, read uniformly, and the time since the previous mark charged to a
+// phase.  Layout of the buffer: 8 header words {workgroups, ticks per second,
+// steps, fields, 0...}, then 8 words per workgroup, one per phase.
+enum Phase : int { kPhSetup = 0, kPhHead = 1, kPhCol = 2, kPhRow = 3, kPhDrain = 4, kPhWait = 5 };
+constexpr int kPhaseWords = 8;
+constexpr int kMaxTimedGroups = 4096;
+struct PhaseTimers {
+    unsigned long long* out;
+    unsigned long long last;
+    unsigned long long acc[kPhaseWords];
+    __device__ __forceinline__ void start(unsigned long long* o) {
+        out = o;
+        for (int k = 0; k < kPhaseWords; ++k) acc[k] = 0;
+        if (out) last = __builtin_amdgcn_s_memrealtime();
+    }
+    __device__ __forceinline__ void mark(int phase) {
+        if (out) {
+            const unsigned long long t = __builtin_amdgcn_s_memrealtime();
+            acc[phase] += t - last;
+            last = t;
+        }
+    }
+    __device__ __forceinline__ void finish(int slot, int steps, int fields) {
+        if (out && threadIdx.x == 0 && slot < kMaxTimedGroups) {
+            if (slot == 0) {
+                out[0] = gridDim.x;
+                out[1] = 100000000ull;
+                out[2] = (unsigned long long)steps;
+                out[3] = (unsigned long long)fields;
+            }
+            for (int k = 0; k < kPhaseWords; ++k) out[kPhaseWords * (slot + 1) + k] = acc[k];
+        }
+    }
+};
+
 __device__ __forceinline__ void grid_sync(unsigned* bar, unsigned gen, bool& abort,
-                                          unsigned* status, unsigned limit) {
+                                          unsigned* status, unsigned limit,
+                                          PhaseTimers* tm = nullptr) {
     __builtin_amdgcn_s_waitcnt(0);
     __syncthreads();
+    if (tm) tm->mark(kPhDrain);
     if (threadIdx.x == 0) {
         const unsigned G = gridDim.x, g = blockIdx.x & 7u;
         const unsigned groups = G < 8u ? G : 8u;
@@ -328,6 +367,7 @@ __device__ __forceinline__ void grid_sync(unsigned* bar, unsigned gen, bool& abo
         }
     }
     __syncthreads();
+    if (tm) tm->mark(kPhWait);
 }
 
 // XCD-aware unit order: workgroups are dealt round-robin over the 8 XCDs, so

@@ -161,3 +161,29 @@ def test_prepared_batch_in_a_captured_graph():
     for job, (o, i) in zip(jobs, prep.results):
         if job["dn"].shape[0] > 0:
             assert bool((o == 7.0).all()) and (i is None or bool((i == 7.0).all()))
+
+
+def test_captured_graph_of_the_64_job_mix():
+    """The 64-job uneven mix (sizes 256-1024 drawn like the paper-scale batch,
+    steps cut to 2-6) captured into one graph: two replays, each job equal bit
+    for bit to its own march."""
+    import paper_1706_02261_amd as bpm
+    specs = synth.batch_job_specs(n_jobs=64, steps_range=(2, 6), budget_bytes=8e9,
+                                  seed_child=12)
+    jobs = make_jobs(specs, seed=64)
+    ref = [separate(j) for j in jobs]
+    prep = bpm.PreparedBatch(jobs)
+    torch.cuda.synchronize()
+    g = torch.cuda.CUDAGraph()
+    with torch.cuda.graph(g):
+        prep.launch()
+    for rep in range(2):
+        for o, i in prep.results:
+            o.fill_(0.0)
+            i.fill_(0.0)
+        torch.cuda.synchronize()
+        g.replay()
+        torch.cuda.synchronize()
+        for k, (o, i) in enumerate(prep.results):
+            assert np.array_equal(o.cpu().numpy(), ref[k][0]), (rep, k)
+            assert np.array_equal(i.cpu().numpy(), ref[k][1]), (rep, k)

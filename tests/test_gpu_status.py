@@ -61,8 +61,10 @@ def test_march_time_out_is_reported(restore_limit):
     bpm.set_wait_limit(0)
     out, inten = bpm.propagate(f, d, 0.2, 0.2, 0.5, 1.33, ws=ws)
     bpm.workspace_status(ws)
+    fresh, fresh_i = bpm.propagate(f, d, 0.2, 0.2, 0.5, 1.33)     # a workspace never timed out
+    assert torch.equal(out, fresh) and torch.equal(inten, fresh_i)
     ru, ri = oracle.bpm_forward(u0, dn, 0.2, 0.2, 0.5, 1.33)
-    assert rel(out.cpu().numpy(), ru) <= 2e-6 and rel(inten.cpu().numpy(), ri) <= 4e-6
+    assert rel(out.cpu().numpy(), ru) <= 1e-5 and rel(inten.cpu().numpy(), ri) <= 1e-5
 
 
 def test_batch_queue_time_out_is_reported(restore_limit):
@@ -87,5 +89,7 @@ def test_batch_queue_time_out_is_reported(restore_limit):
     res = bpm.propagate_batch(jobs, ws=ws)
     bpm.workspace_status(ws)
     for j, (o, i) in zip(jobs, res):
+        so, si = bpm.propagate(j["field"], j["dn"], 0.2, 0.2, 0.5, 1.33)
+        assert torch.equal(o, so) and torch.equal(i, si)
         ru, ri = oracle.bpm_forward(j["u0"], j["dn_h"], 0.2, 0.2, 0.5, 1.33)
-        assert rel(o.cpu().numpy(), ru) <= 2e-6 and rel(i.cpu().numpy(), ri) <= 4e-6
+        assert rel(o.cpu().numpy(), ru) <= 1e-5 and rel(i.cpu().numpy(), ri) <= 1e-5
