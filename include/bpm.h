@@ -316,6 +316,14 @@ int bpm_decode_status(unsigned status_word);
  * kernels launched after the call. */
 int bpm_set_wait_limit(unsigned long long polls);
 
+/* Releases the host resources the library keeps between calls (the pinned
+ * staging buffer and event of bpm_batch_upload / bpm_propagate_batch), after
+ * waiting for the last upload that uses them.  Optional: call it before the
+ * HIP runtime is torn down (e.g. at interpreter exit); the next call that
+ * needs them allocates them again.  Not thread-safe with concurrent batch
+ * uploads. */
+void bpm_release(void);
+
 /* Static text for an error code. */
 const char* bpm_error_string(int code);
 /* Message of the calling thread's last failed call ("" if none). */

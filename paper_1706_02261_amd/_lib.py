@@ -6,6 +6,7 @@ nothing falls back to another implementation.
 """
 from __future__ import annotations
 
+import atexit
 import ctypes
 import os
 
@@ -36,7 +37,7 @@ EXPORTS = (
     "psf_surrogate_layer_geometry", "psf_extract_patches",
     "bpm_point_sources_workspace_size", "bpm_point_sources",
     "bpm_workspace_status", "bpm_decode_status", "bpm_set_wait_limit",
-    "bpm_march_phase_times",
+    "bpm_march_phase_times", "bpm_release",
 )
 PHASE_TIMER_WORDS = 8 + 8 * 4096
 
@@ -120,6 +121,8 @@ def _declare(L):
     L.bpm_psf_readout.argtypes = [_V, _I, _I, _D, _D, _D, _D, _D, _I, _V, _I, _I, _I, _D, _V,
                                   _V, _Z, _V]
     L.bpm_psf_readout.restype = _I
+    L.bpm_release.argtypes = []
+    L.bpm_release.restype = None
     L.bpm_march_phase_times.argtypes = [ctypes.POINTER(Job), _I, _V, _Z, _V, _Z, _V]
     L.bpm_march_phase_times.restype = _I
     L.bpm_workspace_status.argtypes = [_V, _Z, _V]
@@ -144,6 +147,8 @@ def lib():
         L = ctypes.CDLL(LIB_PATH)
         _declare(L)
         _lib = L
+        # free the library's pinned staging while the HIP runtime is alive
+        atexit.register(L.bpm_release)
     return _lib
 
 

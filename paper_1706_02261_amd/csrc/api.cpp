@@ -353,6 +353,18 @@ int batch_device(const bpm_job* jobs, int n_jobs, char* ws, const BatchLayout& L
 
 extern "C" {
 
+void bpm_release(void) {
+    std::lock_guard<std::mutex> lk(g_stage_mu);
+    if (g_stage_done) {
+        (void)hipEventSynchronize(g_stage_done);
+        (void)hipEventDestroy(g_stage_done);
+        g_stage_done = nullptr;
+    }
+    if (g_stage) (void)hipHostFree(g_stage);
+    g_stage = nullptr;
+    g_stage_bytes = 0;
+}
+
 size_t bpm_batch_workspace_size(const bpm_job* jobs, int n_jobs) {
     if (!jobs || n_jobs < 1) return 0;
     for (int i = 0; i < n_jobs; ++i)

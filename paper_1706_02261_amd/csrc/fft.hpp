@@ -186,7 +186,7 @@ struct FftLayout {
 };
 
 // LDS slot of position p (one pad slot every 16 against bank conflicts)
-__device__ __forceinline__ int lds_pad(int p) { return p + (p >> 4); }
+__host__ __device__ constexpr int lds_pad(int p) { return p + (p >> 4); }
 template <int N>
 __host__ __device__ constexpr int lds_size() { return N + N / 16; }
 
@@ -239,22 +239,54 @@ struct Twiddles {
     static constexpr bool kOpaqueIndex = false;
 };
 
-// The same twiddles read on use from a table tw[e] = exp(-2 pi i e / N) in LDS
-// (one table per transform length, shared by the workgroup): no registers held
-// across the passes, one LDS read per twiddle.
+// The same twiddles read on use from a table in LDS (shared by the
+// workgroup): no registers held across the passes, one LDS read per twiddle.
+// The table holds, for every twiddled stage s and every value tp the thread
+// parameter takes in that stage, the row W^(tp m step_s), m = 0 .. R-1, in
+// rows of R + 1 entries (the pad puts the rows of consecutive tp in different
+// banks), so a thread reads its twiddles at a per-stage base plus the
+// compile-time offset m.
+template <int N, int R>
+struct LdsTwiddleTable {
+    static constexpr int S = fft_num_stages(N, R);
+    static constexpr int NS = S > 1 ? S - 1 : 0;  // stages that apply twiddles
+    static constexpr int kRow = R + 1;
+    __host__ __device__ static constexpr int rows(int s) {
+        return s == 0 ? N / R : fft_t_after(N, R, s);
+    }
+    __host__ __device__ static constexpr int offset(int s) {
+        int o = 0;
+        for (int i = 0; i < s; ++i) o += rows(i) * kRow;
+        return o;
+    }
+    __host__ __device__ static constexpr int size() { return offset(NS) > 0 ? offset(NS) : 1; }
+    // fills the table from tw[e] = exp(-2 pi i e / N); threads tid of nthreads
+    __device__ static void fill(float2* tab, const float2* __restrict__ tw, int tid,
+                                int nthreads) {
+        for (int e = tid; e < offset(NS); e += nthreads) {
+            int st = 0;
+            while (e >= offset(st + 1)) ++st;
+            const int row = (e - offset(st)) / kRow, m = (e - offset(st)) % kRow;
+            const int ta = fft_t_after(N, R, st);
+            const int step = N / (fft_radix(N, R, st) * ta);
+            tab[e] = m < R ? tw[(row * m * step) & (N - 1)] : make_float2(0.f, 0.f);
+        }
+    }
+};
+
 template <int N, int R>
 struct LdsTwiddles {
     // used where registers are short: the transforms then hide the thread
     // index from the compiler, so that it recomputes their LDS addresses on
     // every call instead of keeping them all live across the caller's loop
     static constexpr bool kOpaqueIndex = true;
+    using Table = LdsTwiddleTable<N, R>;
     const float2* tab;
     int tau;
     __device__ __forceinline__ float2 get(int s, int m) const {
         const int ta = fft_t_after(N, R, s);
         const int tp = s == 0 ? tau : tau % ta;
-        const int step = N / (fft_radix(N, R, s) * ta);
-        return tab[(tp * m * step) & (N - 1)];
+        return tab[Table::offset(s) + tp * Table::kRow + m];
     }
 };
 
@@ -265,6 +297,16 @@ struct LdsTwiddles {
 // sync(): ordering point over every thread that shares the LDS region.  Within
 // one stage every slot is read and rewritten by the same thread, so a sync is
 // only needed after each LDS write phase.
+//
+// Every LDS access of a stage is p = B + j ta for a per-thread base B and
+// j < r, and B, ta and r are powers of two laid out so that the j ta never
+// carry B's low four bits past a 16-slot boundary: lds_pad(B + j ta) =
+// lds_pad(B) + j ta + (j ta) / 16 (pad_off below).  The transforms therefore
+// compute one base address per stage and reach the slots at compile-time
+// offsets (immediate fields of the LDS instructions), with no per-access
+// index arithmetic.  (The same holds for the stage-0 positions k T + tau.)
+
+__host__ __device__ constexpr int pad_off(int d) { return d + d / 16; }
 
 // Forward transform (exp(-...)).  In: v[i] = x[i*T + tau], natural order.
 // Out: v[reg] = X[fft_freq_of_pos(pos_of_reg(tau, reg))].
@@ -278,25 +320,28 @@ __device__ __forceinline__ void fft_forward(float2 (&v)[R], float2* lds, int tau
     if constexpr (L::S > 1) {
 #pragma unroll
         for (int k = 1; k < R; ++k) v[k] = c_mul(v[k], tw.get(0, k));
+        float2* const w0 = lds + lds_pad(tau) * LSTRIDE;
 #pragma unroll
-        for (int k = 0; k < R; ++k) lds[lds_pad(k * T + tau) * LSTRIDE] = v[k];
+        for (int k = 0; k < R; ++k) w0[pad_off(k * T) * LSTRIDE] = v[k];
         sync();
         static_for<1, L::S>([&](auto sc) {
             constexpr int s = decltype(sc)::value;
             constexpr int r = L::radix(s), ta = L::t_after(s), groups = R / r;
 #pragma unroll
             for (int q = 0; q < groups; ++q) {
-                const int g = tau + T * q, base = (g / ta) * r * ta + g % ta;
+                const int g = tau + T * q;
+                const float2* b = lds + lds_pad((g / ta) * r * ta + g % ta) * LSTRIDE;
 #pragma unroll
-                for (int j = 0; j < r; ++j) v[q * r + j] = lds[lds_pad(base + j * ta) * LSTRIDE];
+                for (int j = 0; j < r; ++j) v[q * r + j] = b[pad_off(j * ta) * LSTRIDE];
             }
             dft_groups<r, -1>(v);
             if constexpr (s < L::S - 1) {
-                const int base = (tau / ta) * r * ta + tau % ta;  // one group per thread
+                // one group per thread
+                float2* b = lds + lds_pad((tau / ta) * r * ta + tau % ta) * LSTRIDE;
 #pragma unroll
                 for (int m = 0; m < r; ++m) {
                     const float2 z = m ? c_mul(v[m], tw.get(s, m)) : v[m];
-                    lds[lds_pad(base + m * ta) * LSTRIDE] = z;
+                    b[pad_off(m * ta) * LSTRIDE] = z;
                 }
                 sync();
             }
@@ -317,24 +362,27 @@ __device__ __forceinline__ void fft_inverse(float2 (&v)[R], float2* lds, int tau
             constexpr int s = L::S - decltype(ic)::value;  // S-1 down to 1
             constexpr int r = L::radix(s), ta = L::t_after(s), groups = R / r;
             if constexpr (s < L::S - 1) {
-                const int base = (tau / ta) * r * ta + tau % ta;  // one group per thread
+                // one group per thread
+                const float2* b = lds + lds_pad((tau / ta) * r * ta + tau % ta) * LSTRIDE;
 #pragma unroll
                 for (int m = 0; m < r; ++m) {
-                    const float2 z = lds[lds_pad(base + m * ta) * LSTRIDE];
+                    const float2 z = b[pad_off(m * ta) * LSTRIDE];
                     v[m] = m ? c_mulc(z, tw.get(s, m)) : z;
                 }
             }
             dft_groups<r, +1>(v);
 #pragma unroll
             for (int q = 0; q < groups; ++q) {
-                const int g = tau + T * q, base = (g / ta) * r * ta + g % ta;
+                const int g = tau + T * q;
+                float2* b = lds + lds_pad((g / ta) * r * ta + g % ta) * LSTRIDE;
 #pragma unroll
-                for (int j = 0; j < r; ++j) lds[lds_pad(base + j * ta) * LSTRIDE] = v[q * r + j];
+                for (int j = 0; j < r; ++j) b[pad_off(j * ta) * LSTRIDE] = v[q * r + j];
             }
             sync();
         });
+        const float2* const w0 = lds + lds_pad(tau) * LSTRIDE;
 #pragma unroll
-        for (int k = 0; k < R; ++k) v[k] = lds[lds_pad(k * T + tau) * LSTRIDE];
+        for (int k = 0; k < R; ++k) v[k] = w0[pad_off(k * T) * LSTRIDE];
 #pragma unroll
         for (int k = 1; k < R; ++k) v[k] = c_mulc(v[k], tw.get(0, k));
     }

@@ -10,11 +10,18 @@
 
 #include "internal.hpp"
 #include "passes.hpp"
+#include "tiled.hpp"
 
 namespace bpm {
 
 // ---------------------------------------------------------------------------
 // persistent forward march
+
+// LDS of the per-thread twiddle tables of both axes (in float2)
+template <int NX, int NY>
+__host__ __device__ constexpr size_t march_twiddle_lds() {
+    return sizeof(float2) * (LdsTwiddleTable<NX, kR>::size() + LdsTwiddleTable<NY, kR>::size());
+}
 
 // LDS of one workgroup's row or column unit (the larger of the two)
 template <int NX, int NY>
@@ -58,7 +65,6 @@ __global__ __launch_bounds__(kBlock, OCC) void march_kernel(MarchArgs a) {
     const int rows_u = (a.ny + units_per_block<NX>() - 1) / units_per_block<NX>();
     const int cols_u = (a.nx + units_per_block<NY>() - 1) / units_per_block<NY>();
     const int all_r = rows_u * a.fields, all_c = cols_u * a.fields;
-    PhaseTimers* tp = a.timers ? &tm : nullptr;
     const size_t plane = (size_t)a.nx * a.ny;
     unsigned nbar = 0;
     bool abort = false;
@@ -71,9 +77,9 @@ __global__ __launch_bounds__(kBlock, OCC) void march_kernel(MarchArgs a) {
         twy.load(a.twy, threadIdx.x / units_per_block<NY>());
     } else {
         float2* tabx = smem + march_data_lds<NX, NY>() / sizeof(float2);
-        float2* taby = tabx + NX;
-        for (int i = threadIdx.x; i < NX; i += kBlock) tabx[i] = a.twx[i];
-        for (int i = threadIdx.x; i < NY; i += kBlock) taby[i] = a.twy[i];
+        float2* taby = tabx + LdsTwiddleTable<NX, kR>::size();
+        LdsTwiddleTable<NX, kR>::fill(tabx, a.twx, threadIdx.x, kBlock);
+        LdsTwiddleTable<NY, kR>::fill(taby, a.twy, threadIdx.x, kBlock);
         __syncthreads();
         twx = TwX{tabx, (int)threadIdx.x % (NX / kR)};
         twy = TwY{taby, (int)threadIdx.x / units_per_block<NY>()};
@@ -98,7 +104,7 @@ __global__ __launch_bounds__(kBlock, OCC) void march_kernel(MarchArgs a) {
     for (int j = 0; j < a.steps; ++j) {
         if (one_row_unit) load_dn<NX>(d, vv / F, a.ny, a.dn[vv % F] + j * plane);
         tm.mark(kPhRow);
-        grid_sync(a.counter, ++nbar, abort, a.status, a.limit, tp);
+        grid_sync(a.counter, ++nbar, abort, a.status, a.limit, tm);
         for (int u = v; u < all_c; u += PAIR * G) {
             const int u2 = u + G;
             const bool two = PAIR == 2 && u2 < all_c;
@@ -113,7 +119,7 @@ __global__ __launch_bounds__(kBlock, OCC) void march_kernel(MarchArgs a) {
                                     nullptr, vb, hb);
         }
         tm.mark(kPhCol);
-        grid_sync(a.counter, ++nbar, abort, a.status, a.limit, tp);
+        grid_sync(a.counter, ++nbar, abort, a.status, a.limit, tm);
         for (int u = v; u < all_r; u += PAIR * G) {
             const int u2 = u + G;
             const bool two = PAIR == 2 && u2 < all_r;
@@ -147,6 +153,87 @@ __global__ __launch_bounds__(kBlock, OCC) void march_kernel(MarchArgs a) {
     }
     __builtin_amdgcn_s_waitcnt(0);
     tm.mark(kPhRow);
+    tm.finish(v, a.steps, a.fields);
+}
+
+// ---------------------------------------------------------------------------
+// two-field march: a barrier per field, tiled field layout
+//
+// For two fields whose passes have one unit per CU each (nx ny = 2^20).  Two
+// workgroups per CU; every workgroup works on one field only, one unit of
+// each of its field's passes, and each field has a grid barrier of its own.
+// Workgroups are laid out so that the two that share a CU (dealt 256 apart:
+// virtual ids 32 apart within one XCD's range) belong to different fields,
+// while an XCD's workgroups of both fields hold the same 32-unit range (one
+// slice of the propagator table in its L2).  When one field's workgroups wait
+// at their barrier, the other field's workgroup on the same CU has the whole
+// CU.  Between the passes the field is kept in the tiled layout of tiled.hpp
+// (in field_out; the head and tail passes convert in place).
+
+template <int NX, int NY>
+__global__ __launch_bounds__(kBlock, 2) void march_duo_kernel(MarchArgs a) {
+    extern __shared__ float2 smem[];
+    PhaseTimers tm;
+    tm.start(a.timers);
+    const int G = gridDim.x, v = virtual_block();
+    const int Gx = G / 8, half = Gx / 2;            // workgroups per XCD, per field and XCD
+    const int f = (v % Gx) / half;                  // this workgroup's field
+    const int unit = (v / Gx) * half + v % half;    // its unit of every pass of that field
+    const size_t plane = (size_t)NX * NY;
+    unsigned* bar = a.counter + f * kFieldBarWords;
+    const unsigned GF = (unsigned)(G / 2);
+    bool abort = false;
+    float2* tabx = smem + march_data_lds<NX, NY>() / sizeof(float2);
+    float2* taby = tabx + LdsTwiddleTable<NX, kR>::size();
+    LdsTwiddleTable<NX, kR>::fill(tabx, a.twx, threadIdx.x, kBlock);
+    LdsTwiddleTable<NY, kR>::fill(taby, a.twy, threadIdx.x, kBlock);
+    __syncthreads();
+    const LdsTwiddles<NX, kR> twx{tabx, (int)threadIdx.x / Tiles<NX, NY>::B};
+    const LdsTwiddles<NY, kR> twy{taby, (int)threadIdx.x / Tiles<NX, NY>::W};
+    float d[kR];
+    for (int i = 0; i < kR; ++i) d[i] = 0.f;
+    tm.mark(kPhSetup);
+    {
+        const RowArgs ra{a.field_in[f], a.work[f], nullptr, nullptr, nullptr, nullptr, nullptr,
+                         a.k0dz};
+        float2 vals[kR];
+        trow_load<NX, NY, kNaturalIn>(unit, ra.src, vals);
+        trow_body<NX, NY, kNaturalIn, kNoOps, kSpecOut>(unit, ra, d, twx, smem, vals);
+    }
+    tm.mark(kPhHead);
+    unsigned gen = 0;
+    auto sync = [&]() {
+        __builtin_amdgcn_s_waitcnt(0);
+        __syncthreads();
+        tm.mark(kPhDrain);
+        ++gen;
+        if (threadIdx.x == 0) bar_arrive(bar, gen, GF, (unsigned)unit);
+        bar_wait(bar, gen, abort, a.status, a.limit, (unsigned)unit);
+        tm.mark(kPhWait);
+    };
+    for (int j = 0; j < a.steps; ++j) {
+        // the unit is the same every step; hidden from the compiler, so that it
+        // recomputes the passes' addresses instead of keeping them all live
+        int u = unit;
+        asm volatile("" : "+s"(u));
+        float2 vals[kR], h[kR];
+        trow_dn<NX, NY>(u, a.dn[f] + (size_t)j * plane, d);
+        sync();
+        tcol_load<NX, NY>(u, a.work[f], a.H, vals, h);
+        tcol_body<NX, NY>(u, a.work[f], twy, smem, vals, h);
+        tm.mark(kPhCol);
+        sync();
+        asm volatile("" : "+s"(u));
+        trow_load<NX, NY, kSpecIn>(u, a.work[f], vals);
+        const RowArgs ra{a.work[f], a.work[f],
+                         a.inten[f] ? a.inten[f] + (size_t)j * plane : nullptr, nullptr, nullptr,
+                         nullptr, nullptr, a.k0dz};
+        if (j + 1 < a.steps)
+            trow_body<NX, NY, kSpecIn, kScreen, kSpecOut>(u, ra, d, twx, smem, vals);
+        else
+            trow_body<NX, NY, kSpecIn, kScreen, kNaturalOut>(u, ra, d, twx, smem, vals);
+        tm.mark(kPhRow);
+    }
     tm.finish(v, a.steps, a.fields);
 }
 
@@ -348,12 +435,22 @@ hipError_t launch_forward_x(const MarchArgs& a, hipStream_t s) {
     return dispatch_ny(a.ny, [&](auto yc) {
         constexpr int NY = decltype(yc)::value;
         void* args[] = {const_cast<MarchArgs*>(&a)};
+        // two fields whose passes have one unit per CU each: a barrier per field
+        const int cus = device_cus();
+        if constexpr (units_per_block<NX>() * units_per_block<NY>() == 16) {
+            if (a.fields == 2 && cus % 16 == 0 && NY / units_per_block<NX>() == cus &&
+                NX / units_per_block<NY>() == cus)
+                return hipLaunchCooperativeKernel(
+                    reinterpret_cast<const void*>(&march_duo_kernel<NX, NY>), dim3(2 * cus),
+                    dim3(kBlock), args,
+                    (unsigned)(march_data_lds<NX, NY>() + march_twiddle_lds<NX, NY>()), s);
+        }
         if constexpr (NX >= 512 && NY >= 512) {
             if (a.fields >= 2)
                 return hipLaunchCooperativeKernel(
                     reinterpret_cast<const void*>(&march_kernel<NX, NY, 2>),
                     dim3(persistent_grid<NX, NY>(a.nx, a.ny, a.fields, 2)), dim3(kBlock), args,
-                    (unsigned)(march_data_lds<NX, NY>() + sizeof(float2) * (NX + NY)), s);
+                    (unsigned)(march_data_lds<NX, NY>() + march_twiddle_lds<NX, NY>()), s);
         }
         return hipLaunchCooperativeKernel(reinterpret_cast<const void*>(&march_kernel<NX, NY, 1>),
                                           dim3(persistent_grid<NX, NY>(a.nx, a.ny, a.fields)),

@@ -14,7 +14,8 @@ namespace bpm {
 
 constexpr int kR = 16;           // complex values per thread
 constexpr int kBlock = 256;      // threads per workgroup
-constexpr int kBarWords = 1024;  // grid-barrier words (4 KiB) in the plan
+constexpr int kFieldBarWords = 1024;  // words of one grid barrier (4 KiB)
+constexpr int kBarWords = 8 * kFieldBarWords;  // one barrier per lockstep field, in the plan
 
 // rows (or columns) of length N one workgroup of BLK threads transforms at once
 template <int N, int BLK = kBlock>
@@ -337,11 +338,10 @@ struct PhaseTimers {
 };
 
 __device__ __forceinline__ void grid_sync(unsigned* bar, unsigned gen, bool& abort,
-                                          unsigned* status, unsigned limit,
-                                          PhaseTimers* tm = nullptr) {
+                                          unsigned* status, unsigned limit, PhaseTimers& tm) {
     __builtin_amdgcn_s_waitcnt(0);
     __syncthreads();
-    if (tm) tm->mark(kPhDrain);
+    tm.mark(kPhDrain);
     if (threadIdx.x == 0) {
         const unsigned G = gridDim.x, g = blockIdx.x & 7u;
         const unsigned groups = G < 8u ? G : 8u;
@@ -367,7 +367,57 @@ __device__ __forceinline__ void grid_sync(unsigned* bar, unsigned gen, bool& abo
         }
     }
     __syncthreads();
-    if (tm) tm->mark(kPhWait);
+    tm.mark(kPhWait);
+}
+
+// grid_sync without timers
+__device__ __forceinline__ void grid_sync(unsigned* bar, unsigned gen, bool& abort,
+                                          unsigned* status, unsigned limit) {
+    PhaseTimers none;
+    none.start(nullptr);
+    grid_sync(bar, gen, abort, status, limit, none);
+}
+
+// The same barrier split into its two halves, for marches that run several
+// fields with one barrier each and do other work between arriving at one and
+// waiting on it.  bar_arrive: thread 0, after the workgroup's stores of the
+// phase are complete (s_waitcnt and a workgroup barrier before the call).
+// bar_wait: every thread; returns once `gen` phases have completed everywhere.
+// G workgroups take part; `index` (0 .. G-1) is this workgroup's place among
+// them, which picks its group counter.
+__device__ __forceinline__ void bar_arrive(unsigned* bar, unsigned gen, unsigned G,
+                                           unsigned index) {
+    const unsigned g = index & 7u;
+    const unsigned groups = G < 8u ? G : 8u;
+    const unsigned members = (G - g + 7u) / 8u;
+    const unsigned old = __hip_atomic_fetch_add(bar + 32 * g, 1u, __ATOMIC_RELAXED,
+                                                __HIP_MEMORY_SCOPE_AGENT);
+    if (old + 1u == gen * members) {
+        const unsigned o2 = __hip_atomic_fetch_add(bar + 512, 1u, __ATOMIC_RELAXED,
+                                                   __HIP_MEMORY_SCOPE_AGENT);
+        if (o2 + 1u == gen * groups)
+            for (unsigned k = 0; k < groups; ++k)
+                __hip_atomic_store(bar + 256 + 32 * k, gen, __ATOMIC_RELAXED,
+                                   __HIP_MEMORY_SCOPE_AGENT);
+    }
+}
+
+__device__ __forceinline__ void bar_wait(const unsigned* bar, unsigned gen, bool& abort,
+                                         unsigned* status, unsigned limit, unsigned index) {
+    if (threadIdx.x == 0) {
+        const unsigned g = index & 7u;
+        unsigned spins = 0;
+        while (!abort && __hip_atomic_load(bar + 256 + 32 * g, __ATOMIC_RELAXED,
+                                           __HIP_MEMORY_SCOPE_AGENT) < gen) {
+            if (++spins > limit) {
+                __hip_atomic_store(const_cast<unsigned*>(bar) + 544, 1u, __ATOMIC_RELAXED,
+                                   __HIP_MEMORY_SCOPE_AGENT);
+                record_timeout(status, kStatusBarrier);
+                abort = true;
+            }
+        }
+    }
+    __syncthreads();
 }
 
 // XCD-aware unit order: workgroups are dealt round-robin over the 8 XCDs, so

@@ -89,10 +89,13 @@ def test_batch_of_the_uneven_mix():
 
 
 @pytest.mark.parametrize("shape,n_jobs", [((256, 512, 9), 3), ((128, 128, 5), 8),
-                                          ((64, 64, 3), 9), ((1024, 1024, 6), 2)])
+                                          ((64, 64, 3), 9), ((1024, 1024, 6), 2),
+                                          ((1024, 1024, 4), 3), ((1024, 1024, 3), 8),
+                                          ((2048, 512, 3), 2), ((512, 2048, 3), 4)])
 def test_lockstep_batch_of_one_geometry(shape, n_jobs):
     """Jobs of one geometry (up to 8) march in lockstep in the cooperative
-    kernel; 9 fall back to the work queue.  Either way every job equals its own
+    kernel (the pipelined one where every pass of a field has one unit per CU:
+    1024^2, 2048 x 512, 512 x 2048); 9 fall back to the work queue.  Either way every job equals its own
     march bit for bit; one job writes its output over its input and one skips
     the intensity volume."""
     import paper_1706_02261_amd as bpm
