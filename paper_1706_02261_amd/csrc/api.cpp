@@ -392,7 +392,8 @@ int bpm_propagate_batch(const bpm_job* jobs, int n_jobs, void* workspace,
         const bpm_job& j0 = jobs[0];
         const bpm::Geom g{j0.nx, j0.ny, j0.steps, j0.dx, j0.dz, j0.wavelength, j0.n0};
         const bpm::Plan p = bpm::plan_carve(ws + L.plan_off[0], j0.nx, j0.ny);
-        if ((rc = device_status(bpm::launch_plan(g, p, true, s), "batch plan"))) return rc;
+        const bool tiled = bpm::march_tiled(j0.nx, j0.ny, n_jobs);
+        if ((rc = device_status(bpm::launch_plan(g, p, true, s, tiled), "batch plan"))) return rc;
         bpm::MarchIO io[bpm::kMaxFields];
         for (int i = 0; i < n_jobs; ++i)
             io[i] = bpm::MarchIO{jobs[i].field_in, jobs[i].dn, jobs[i].field_out,
@@ -428,7 +429,8 @@ int bpm_march_phase_times(const bpm_job* jobs, int n_jobs, void* workspace,
     const bpm_job& j0 = jobs[0];
     const bpm::Geom g{j0.nx, j0.ny, j0.steps, j0.dx, j0.dz, j0.wavelength, j0.n0};
     const bpm::Plan p = bpm::plan_carve(static_cast<char*>(workspace) + L.plan_off[0], j0.nx, j0.ny);
-    if ((rc = device_status(bpm::launch_plan(g, p, true, s), "plan"))) return rc;
+    const bool tiled = bpm::march_tiled(j0.nx, j0.ny, n_jobs);
+    if ((rc = device_status(bpm::launch_plan(g, p, true, s, tiled), "plan"))) return rc;
     if ((rc = device_status(hipMemsetAsync(timers, 0, timer_bytes, s), "timers"))) return rc;
     bpm::MarchIO io[bpm::kMaxFields];
     for (int i = 0; i < n_jobs; ++i)

@@ -42,7 +42,12 @@ size_t plan_bytes(int nx, int ny);
 // compute units of the current device (0 when the query fails)
 int device_cus();
 Plan plan_carve(void* ws, int nx, int ny);
-hipError_t launch_plan(const Geom& g, const Plan& p, bool with_h, hipStream_t s);
+// tiled_h: the propagator table in the tiled layout of the two-field march
+hipError_t launch_plan(const Geom& g, const Plan& p, bool with_h, hipStream_t s,
+                       bool tiled_h = false);
+// whether `fields` lockstep fields of this geometry take the two-field tiled
+// march (and so need a tiled propagator table)
+bool march_tiled(int nx, int ny, int fields);
 
 // Forward march through `steps` slices; field_out doubles as working buffer.
 // Up to kMaxFields fields of one geometry (one plan) march in lockstep in one

@@ -70,7 +70,7 @@ __global__ void plan_kernel(unsigned* __restrict__ status, float2* __restrict__ 
                             float2* __restrict__ twx, float2* __restrict__ twy,
                             int* __restrict__ permx, int* __restrict__ permy,
                             unsigned* __restrict__ counter, int nx, int ny, double dx, double dz,
-                            double lam, double n0, int with_h) {
+                            double lam, double n0, int with_h, int tiled) {
     if (blockIdx.x == 0) {
         for (int i = threadIdx.x; i < kBarWords; i += blockDim.x) counter[i] = 0u;
         // a workspace seen for the first time: clear its sticky status bits
@@ -105,7 +105,13 @@ __global__ void plan_kernel(unsigned* __restrict__ status, float2* __restrict__ 
                 sincos(dz * kz, &sv, &cv);
                 h = make_float2((float)(cv * scale), (float)(sv * scale));
             }
-            H[e] = h;
+            if (tiled) {
+                // B x W tiles of one 128-byte line (B = 4096 / nx, W = 4096 / ny)
+                const long B = 4096 / nx, W = 4096 / ny;
+                H[((py / B) * (nx / W) + px / W) * 16 + (py % B) * W + px % W] = h;
+            } else {
+                H[e] = h;
+            }
         } else if (e < nh + nx + ny) {
             const long t = e - nh;
             const int n = t < nx ? nx : ny;
@@ -121,13 +127,21 @@ __global__ void plan_kernel(unsigned* __restrict__ status, float2* __restrict__ 
     }
 }
 
-hipError_t launch_plan(const Geom& g, const Plan& p, bool with_h, hipStream_t s) {
+bool march_tiled(int nx, int ny, int fields) {
+    const int cus = device_cus();
+    if (nx <= 0 || ny <= 0 || 4096 % nx != 0 || 4096 % ny != 0 || cus <= 0) return false;
+    const int B = 4096 / nx, W = 4096 / ny;  // rows of a row unit, columns of a column unit
+    return fields == 2 && B * W == 16 && cus % 16 == 0 && ny / B == cus && nx / W == cus;
+}
+
+hipError_t launch_plan(const Geom& g, const Plan& p, bool with_h, hipStream_t s, bool tiled_h) {
     const long total = (with_h ? (long)g.nx * g.ny : 0) + 2L * (g.nx + g.ny);
     const int threads = 256;
     const long blocks = (total + threads - 1) / threads;
     plan_kernel<<<(unsigned)(blocks < 4096 ? blocks : 4096), threads, 0, s>>>(
         (unsigned*)p.status, (float2*)p.H, (float2*)p.twx, (float2*)p.twy, (int*)p.permx, (int*)p.permy,
-        (unsigned*)p.counter, g.nx, g.ny, g.dx, g.dz, g.wavelength, g.n0, with_h ? 1 : 0);
+        (unsigned*)p.counter, g.nx, g.ny, g.dx, g.dz, g.wavelength, g.n0, with_h ? 1 : 0,
+        tiled_h ? 1 : 0);
     return hipGetLastError();
 }
 

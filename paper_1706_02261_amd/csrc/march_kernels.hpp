@@ -168,7 +168,8 @@ __global__ __launch_bounds__(kBlock, OCC) void march_kernel(MarchArgs a) {
 // slice of the propagator table in its L2).  When one field's workgroups wait
 // at their barrier, the other field's workgroup on the same CU has the whole
 // CU.  Between the passes the field is kept in the tiled layout of tiled.hpp
-// (in field_out; the head and tail passes convert in place).
+// (in field_out; the head and tail passes convert in place), and the plan
+// stores the propagator table in the same layout.
 
 template <int NX, int NY>
 __global__ __launch_bounds__(kBlock, 2) void march_duo_kernel(MarchArgs a) {
@@ -202,12 +203,16 @@ __global__ __launch_bounds__(kBlock, 2) void march_duo_kernel(MarchArgs a) {
     }
     tm.mark(kPhHead);
     unsigned gen = 0;
-    auto sync = [&]() {
+    // a pass's stores complete, then the arrival; read-only data of the next
+    // passes is fetched between the arrival and the wait
+    auto arrive = [&]() {
         __builtin_amdgcn_s_waitcnt(0);
         __syncthreads();
         tm.mark(kPhDrain);
         ++gen;
         if (threadIdx.x == 0) bar_arrive(bar, gen, GF, (unsigned)unit);
+    };
+    auto wait = [&]() {
         bar_wait(bar, gen, abort, a.status, a.limit, (unsigned)unit);
         tm.mark(kPhWait);
     };
@@ -217,12 +222,15 @@ __global__ __launch_bounds__(kBlock, 2) void march_duo_kernel(MarchArgs a) {
         int u = unit;
         asm volatile("" : "+s"(u));
         float2 vals[kR], h[kR];
+        arrive();
         trow_dn<NX, NY>(u, a.dn[f] + (size_t)j * plane, d);
-        sync();
-        tcol_load<NX, NY>(u, a.work[f], a.H, vals, h);
+        tcol_h<NX, NY>(u, a.H, h);
+        wait();
+        tcol_load<NX, NY>(u, a.work[f], vals);
         tcol_body<NX, NY>(u, a.work[f], twy, smem, vals, h);
         tm.mark(kPhCol);
-        sync();
+        arrive();
+        wait();
         asm volatile("" : "+s"(u));
         trow_load<NX, NY, kSpecIn>(u, a.work[f], vals);
         const RowArgs ra{a.work[f], a.work[f],
@@ -438,8 +446,7 @@ hipError_t launch_forward_x(const MarchArgs& a, hipStream_t s) {
         // two fields whose passes have one unit per CU each: a barrier per field
         const int cus = device_cus();
         if constexpr (units_per_block<NX>() * units_per_block<NY>() == 16) {
-            if (a.fields == 2 && cus % 16 == 0 && NY / units_per_block<NX>() == cus &&
-                NX / units_per_block<NY>() == cus)
+            if (march_tiled(NX, NY, a.fields))
                 return hipLaunchCooperativeKernel(
                     reinterpret_cast<const void*>(&march_duo_kernel<NX, NY>), dim3(2 * cus),
                     dim3(kBlock), args,

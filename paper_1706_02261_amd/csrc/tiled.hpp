@@ -85,19 +85,26 @@ __device__ __forceinline__ void trow_body(int unit, const RowArgs& a, const floa
 }
 
 // Column unit `unit` (slots unit*W .. unit*W + W-1): thread (w, t) = (tid % W,
-// tid / W) holds column unit*W + w at rows i T + t; the propagator is read from
-// the plan's natural-layout table (cache-resident).
+// tid / W) holds column unit*W + w at rows i T + t.
 template <int NX, int NY>
-__device__ __forceinline__ void tcol_load(int unit, const float2* work,
-                                          const float2* __restrict__ H, float2 (&v)[kR],
-                                          float2 (&h)[kR]) {
+__device__ __forceinline__ void tcol_load(int unit, const float2* work, float2 (&v)[kR]) {
     using TL = Tiles<NX, NY>;
     constexpr int T = NY / kR;
     const int w = threadIdx.x % TL::W, t = threadIdx.x / TL::W, x = unit * TL::W + w;
 #pragma unroll
     for (int i = 0; i < kR; ++i) v[i] = ld_shared_field(work + TL::off(i * T + t, x));
+}
+
+// the unit's propagator values, from a table stored in the same tiled layout
+// (read-only: fetched before the grid barrier that guards the field)
+template <int NX, int NY>
+__device__ __forceinline__ void tcol_h(int unit, const float2* __restrict__ H,
+                                       float2 (&h)[kR]) {
+    using TL = Tiles<NX, NY>;
+    constexpr int T = NY / kR;
+    const int w = threadIdx.x % TL::W, t = threadIdx.x / TL::W, x = unit * TL::W + w;
 #pragma unroll
-    for (int r = 0; r < kR; ++r) h[r] = H[(size_t)(r * T + t) * NX + x];
+    for (int r = 0; r < kR; ++r) h[r] = H[TL::off(r * T + t, x)];
 }
 
 template <int NX, int NY, typename Tw>
