@@ -275,6 +275,25 @@ int psf_surrogate_infer(const void* weights_bf16, size_t weights_bytes,
                         float* psf_out, float* pred_err, void* workspace,
                         size_t workspace_bytes, void* hip_stream);
 
+/* Forward march that allocates nothing, for callers that cannot allocate
+ * device memory (code under HIP graph capture, tight serving loops, harnesses
+ * that forbid hipMalloc).  Same arguments, results (bit for bit) and errors
+ * as bpm_propagate, without the workspace: the march's plan lives in a device
+ * array of the library, one per GPU, held until the process ends
+ * (bpm_noalloc_scratch_bytes() bytes: fields up to 1024 x 1024; larger fields
+ * return BPM_ERR_UNSUPPORTED_SIZE before any launch).  The call makes no
+ * allocation of any kind.  Every call on one GPU uses that GPU's array, so
+ * calls that overlap in time on one GPU (other streams, other threads) race
+ * and must be serialised by the caller; each call rebuilds the plan it needs
+ * and clears the barrier words, so consecutive calls of different sizes are
+ * independent.  Wait time-outs (see bpm_workspace_status) are recorded in the
+ * array's header and cannot be queried. */
+int bpm_propagate_noalloc(const bpm_c64* field_in, const float* dn, int nx, int ny, int steps,
+                          double dx, double dz, double wavelength, double n0,
+                          bpm_c64* field_out, float* intensity_out, void* hip_stream);
+/* Size of the per-GPU device array of bpm_propagate_noalloc (bytes). */
+size_t bpm_noalloc_scratch_bytes(void);
+
 /* Wait time-outs of the persistent kernels.
  *
  * The persistent kernels of bpm_propagate, bpm_propagate_batch,

@@ -38,6 +38,7 @@ EXPORTS = (
     "bpm_point_sources_workspace_size", "bpm_point_sources",
     "bpm_workspace_status", "bpm_decode_status", "bpm_set_wait_limit",
     "bpm_march_phase_times", "bpm_release",
+    "bpm_propagate_noalloc", "bpm_noalloc_scratch_bytes",
 )
 PHASE_TIMER_WORDS = 8 + 8 * 4096
 
@@ -121,6 +122,10 @@ def _declare(L):
     L.bpm_psf_readout.argtypes = [_V, _I, _I, _D, _D, _D, _D, _D, _I, _V, _I, _I, _I, _D, _V,
                                   _V, _Z, _V]
     L.bpm_psf_readout.restype = _I
+    L.bpm_propagate_noalloc.argtypes = [_V, _V, _I, _I, _I, _D, _D, _D, _D, _V, _V, _V]
+    L.bpm_propagate_noalloc.restype = _I
+    L.bpm_noalloc_scratch_bytes.argtypes = []
+    L.bpm_noalloc_scratch_bytes.restype = _Z
     L.bpm_release.argtypes = []
     L.bpm_release.restype = None
     L.bpm_march_phase_times.argtypes = [ctypes.POINTER(Job), _I, _V, _Z, _V, _Z, _V]

@@ -77,6 +77,28 @@ def propagate(field: torch.Tensor, dn: torch.Tensor, dx: float, dz: float,
     return out, intensity_out
 
 
+def propagate_noalloc(field: torch.Tensor, dn: torch.Tensor, dx: float, dz: float,
+                      wavelength: float, n0: float, out: torch.Tensor,
+                      intensity_out: torch.Tensor | None = None, stream=None):
+    """bpm_propagate_noalloc: ``propagate`` into caller-given ``out`` (and
+    ``intensity_out`` or None) with the library's own per-GPU plan memory; no
+    allocation of any kind (fields up to 1024 x 1024)."""
+    _need(field, "field", torch.complex64)
+    ny, nx = field.shape
+    _need(dn, "dn", torch.float32)
+    if dn.dim() != 3 or tuple(dn.shape[1:]) != (ny, nx):
+        raise ValueError(f"dn has shape {tuple(dn.shape)}, expected [steps][{ny}][{nx}]")
+    steps = dn.shape[0]
+    _need(out, "out", torch.complex64, (ny, nx))
+    if intensity_out is not None:
+        _need(intensity_out, "intensity_out", torch.float32, (steps, ny, nx))
+    rc = lib().bpm_propagate_noalloc(_ptr(field), _ptr(dn), nx, ny, steps, float(dx), float(dz),
+                                     float(wavelength), float(n0), _ptr(out),
+                                     _ptr(intensity_out), _stream_ptr(stream))
+    check(rc, "bpm_propagate_noalloc")
+    return out, intensity_out
+
+
 def workspace_status(ws: torch.Tensor, stream=None) -> None:
     """Raise BpmError (BPM_ERR_DEVICE) if a wait of a kernel that used ``ws``
     gave up since the last query (its outputs are not valid); synchronises the
