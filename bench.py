@@ -448,6 +448,9 @@ def main():
                     help="only the surrogate vs BPM PSF rates (for profiling those kernels)")
     ap.add_argument("--no-extra", action="store_true",
                     help="skip the adjoint and uneven-batch rates")
+    ap.add_argument("--tune", action="store_true",
+                    help="time every kernel the march offers for the benchmark's shape first, "
+                         "keep the fastest (launch-shape tuner) and record it in the cache")
     ap.add_argument("--phase-times", action="store_true",
                     help="also run the timed launch once with per-workgroup phase timers and "
                          "report the split of a step into pass work, store drain and barrier "
@@ -495,6 +498,13 @@ def main():
                              for j in jobs])
     ws = B.workspace(B.lib().bpm_batch_workspace_size(arr, 2), dev)
     stream = torch.cuda.current_stream(dev)
+    from paper_1706_02261_amd import tune
+    tuned = tune.tune([(g.nx, g.ny, len(jobs))], steps=16) if args.tune else None
+    if tuned:
+        tune.save(tuned)
+    else:
+        tune.load()
+    variant = tune.VARIANTS[tune.current_variant(g.nx, g.ny, len(jobs))]
 
     def march():
         bpm.propagate_batch(jobs, ws=ws, stream=stream)
@@ -551,8 +561,10 @@ def main():
             "traffic": traffic,
             "traffic_bytes_per_voxel_step": None if traffic_bytes is None
             else round(traffic_bytes / voxel_steps, 2),
-            "kernel": "march_kernel, 2 fields in lockstep (one launch per step, plan "
-                      "kernel included)",
+            "kernel": f"march ({variant} kernel), 2 fields in one launch per step, plan "
+                      "kernel included",
+            "launch_variant": variant,
+            "tuner_ms": None if not tuned else next(iter(tuned.values()))["ms"],
             "launch_ms": round(launch_ms, 4),
             "bytes_per_voxel_step": BYTES_PER_VOXEL_STEP,
             "fp32_tflops": round(FLOP_PER_VOXEL_STEP * voxel_steps / (launch_ms / 1e3) / 1e12, 2),

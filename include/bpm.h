@@ -275,6 +275,38 @@ int psf_surrogate_infer(const void* weights_bf16, size_t weights_bytes,
                         float* psf_out, float* pred_err, void* workspace,
                         size_t workspace_bytes, void* hip_stream);
 
+/* Kernels of the forward march (bpm_propagate, and the lockstep path of
+ * bpm_propagate_batch for 1-8 jobs of one geometry), chosen per shape
+ * (nx, ny, number of lockstep fields):
+ *   BPM_MARCH_ONE_PER_CU   one 256-thread workgroup per CU, twiddles in
+ *                          registers, a workgroup's units two at a time;
+ *   BPM_MARCH_TWO_PER_CU   two workgroups per CU, twiddles in LDS (nx, ny >= 512);
+ *   BPM_MARCH_TILED_PAIR   two fields with a grid barrier each, two workgroups
+ *                          per CU holding different fields, the field kept in
+ *                          128-byte tiles between passes (two fields with
+ *                          nx ny = 2^20 on a device of 256 CUs);
+ *   BPM_MARCH_AUTO         the built-in choice (tiled pair where eligible, two
+ *                          per CU for several fields of sides >= 512, else one).
+ * All give bit-identical results.  A launch-shape tuner (the package's
+ * tune.py) times the eligible kernels of a shape on the device and records
+ * the fastest with bpm_set_march_variant. */
+enum {
+    BPM_MARCH_AUTO = 0,
+    BPM_MARCH_ONE_PER_CU = 1,
+    BPM_MARCH_TWO_PER_CU = 2,
+    BPM_MARCH_TILED_PAIR = 3
+};
+/* The kernel a march of this shape takes now (BPM_MARCH_ONE_PER_CU ..), or
+ * BPM_ERR_INVALID_ARG for unsupported sizes or fields outside 1 .. 8. */
+int bpm_march_variant(int nx, int ny, int fields);
+/* 1 if `variant` can run this shape on the current device, else 0. */
+int bpm_march_variant_eligible(int nx, int ny, int fields, int variant);
+/* Process-wide choice of the kernel for a shape: BPM_MARCH_AUTO clears it;
+ * a variant that cannot run the shape returns BPM_ERR_INVALID_ARG.  Applies
+ * to calls made after it returns; do not change a shape's choice while a
+ * call of that shape is being issued on another thread. */
+int bpm_set_march_variant(int nx, int ny, int fields, int variant);
+
 /* Forward march that allocates nothing, for callers that cannot allocate
  * device memory (code under HIP graph capture, tight serving loops, harnesses
  * that forbid hipMalloc).  Same arguments, results (bit for bit) and errors

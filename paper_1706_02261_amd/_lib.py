@@ -39,7 +39,12 @@ EXPORTS = (
     "bpm_workspace_status", "bpm_decode_status", "bpm_set_wait_limit",
     "bpm_march_phase_times", "bpm_release",
     "bpm_propagate_noalloc", "bpm_noalloc_scratch_bytes",
+    "bpm_march_variant", "bpm_march_variant_eligible", "bpm_set_march_variant",
 )
+BPM_MARCH_AUTO = 0
+BPM_MARCH_ONE_PER_CU = 1
+BPM_MARCH_TWO_PER_CU = 2
+BPM_MARCH_TILED_PAIR = 3
 PHASE_TIMER_WORDS = 8 + 8 * 4096
 
 
@@ -122,6 +127,12 @@ def _declare(L):
     L.bpm_psf_readout.argtypes = [_V, _I, _I, _D, _D, _D, _D, _D, _I, _V, _I, _I, _I, _D, _V,
                                   _V, _Z, _V]
     L.bpm_psf_readout.restype = _I
+    L.bpm_march_variant.argtypes = [_I, _I, _I]
+    L.bpm_march_variant.restype = _I
+    L.bpm_march_variant_eligible.argtypes = [_I, _I, _I, _I]
+    L.bpm_march_variant_eligible.restype = _I
+    L.bpm_set_march_variant.argtypes = [_I, _I, _I, _I]
+    L.bpm_set_march_variant.restype = _I
     L.bpm_propagate_noalloc.argtypes = [_V, _V, _I, _I, _I, _D, _D, _D, _D, _V, _V, _V]
     L.bpm_propagate_noalloc.restype = _I
     L.bpm_noalloc_scratch_bytes.argtypes = []

@@ -66,6 +66,29 @@ int bpm_set_wait_limit(unsigned long long polls) {
     return BPM_OK;
 }
 
+int bpm_march_variant(int nx, int ny, int fields) {
+    if (!pow2_in_range(nx) || !pow2_in_range(ny) || fields < 1 || fields > bpm::kMaxFields)
+        return fail(BPM_ERR_INVALID_ARG, "nx=%d ny=%d fields=%d: sizes must be powers of two in "
+                    "[32, 2048] and fields in [1, %d]", nx, ny, fields, bpm::kMaxFields);
+    return bpm::march_variant(nx, ny, fields);
+}
+
+int bpm_march_variant_eligible(int nx, int ny, int fields, int variant) {
+    return bpm::march_variant_eligible(nx, ny, fields, variant) ? 1 : 0;
+}
+
+int bpm_set_march_variant(int nx, int ny, int fields, int variant) {
+    if (!pow2_in_range(nx) || !pow2_in_range(ny) || fields < 1 || fields > bpm::kMaxFields)
+        return fail(BPM_ERR_INVALID_ARG, "nx=%d ny=%d fields=%d: sizes must be powers of two in "
+                    "[32, 2048] and fields in [1, %d]", nx, ny, fields, bpm::kMaxFields);
+    if (variant < BPM_MARCH_AUTO || variant > BPM_MARCH_TILED_PAIR)
+        return fail(BPM_ERR_INVALID_ARG, "variant=%d is not a BPM_MARCH_* value", variant);
+    if (bpm::set_march_variant(nx, ny, fields, variant) != 0)
+        return fail(BPM_ERR_INVALID_ARG, "variant %d cannot run %d x %d with %d field(s) on this "
+                    "device", variant, nx, ny, fields);
+    return BPM_OK;
+}
+
 int bpm_decode_status(unsigned status_word) {
     if (status_word == 0) return BPM_OK;
     std::string what;
@@ -392,13 +415,15 @@ int bpm_propagate_batch(const bpm_job* jobs, int n_jobs, void* workspace,
         const bpm_job& j0 = jobs[0];
         const bpm::Geom g{j0.nx, j0.ny, j0.steps, j0.dx, j0.dz, j0.wavelength, j0.n0};
         const bpm::Plan p = bpm::plan_carve(ws + L.plan_off[0], j0.nx, j0.ny);
-        const bool tiled = bpm::march_tiled(j0.nx, j0.ny, n_jobs);
+        const int var = bpm::march_variant(j0.nx, j0.ny, n_jobs);
+        const bool tiled = var == bpm::kMarchTiledPair;
         if ((rc = device_status(bpm::launch_plan(g, p, true, s, tiled), "batch plan"))) return rc;
         bpm::MarchIO io[bpm::kMaxFields];
         for (int i = 0; i < n_jobs; ++i)
             io[i] = bpm::MarchIO{jobs[i].field_in, jobs[i].dn, jobs[i].field_out,
                                  jobs[i].intensity_out};
-        return device_status(bpm::launch_forward(g, p, io, n_jobs, s), "batch march");
+        return device_status(bpm::launch_forward(g, p, io, n_jobs, s, nullptr, var),
+                             "batch march");
     }
 
     if ((rc = batch_tables(jobs, n_jobs, ws, L, s))) return rc;
@@ -429,13 +454,14 @@ int bpm_march_phase_times(const bpm_job* jobs, int n_jobs, void* workspace,
     const bpm_job& j0 = jobs[0];
     const bpm::Geom g{j0.nx, j0.ny, j0.steps, j0.dx, j0.dz, j0.wavelength, j0.n0};
     const bpm::Plan p = bpm::plan_carve(static_cast<char*>(workspace) + L.plan_off[0], j0.nx, j0.ny);
-    const bool tiled = bpm::march_tiled(j0.nx, j0.ny, n_jobs);
+    const int var = bpm::march_variant(j0.nx, j0.ny, n_jobs);
+    const bool tiled = var == bpm::kMarchTiledPair;
     if ((rc = device_status(bpm::launch_plan(g, p, true, s, tiled), "plan"))) return rc;
     if ((rc = device_status(hipMemsetAsync(timers, 0, timer_bytes, s), "timers"))) return rc;
     bpm::MarchIO io[bpm::kMaxFields];
     for (int i = 0; i < n_jobs; ++i)
         io[i] = bpm::MarchIO{jobs[i].field_in, jobs[i].dn, jobs[i].field_out, jobs[i].intensity_out};
-    return device_status(bpm::launch_forward(g, p, io, n_jobs, s, timers), "timed march");
+    return device_status(bpm::launch_forward(g, p, io, n_jobs, s, timers, var), "timed march");
 }
 
 int bpm_batch_upload(const bpm_job* jobs, int n_jobs, void* workspace, size_t workspace_bytes,

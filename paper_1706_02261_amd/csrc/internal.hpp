@@ -10,6 +10,21 @@ namespace bpm {
 constexpr size_t kAlign = 256;
 inline size_t align_up(size_t v) { return (v + kAlign - 1) / kAlign * kAlign; }
 
+// Kernels of the forward march (values of bpm.h's BPM_MARCH_*): one
+// workgroup per CU with register twiddles; two per CU with LDS twiddles; the
+// two-field tiled march.  march_variant gives the one a march of `fields`
+// lockstep fields of this geometry takes: the override set for the shape
+// (bpm_set_march_variant, e.g. from the launch-shape tuner) when eligible,
+// else the built-in choice.
+enum MarchVariant : int { kMarchAuto = 0, kMarchOnePerCu = 1, kMarchTwoPerCu = 2,
+                          kMarchTiledPair = 3 };
+bool march_variant_eligible(int nx, int ny, int fields, int variant);
+int march_variant(int nx, int ny, int fields);
+int set_march_variant(int nx, int ny, int fields, int variant);  // 0 ok, -1 ineligible
+// whether such a march takes the two-field tiled kernel (and so needs a tiled
+// propagator table)
+bool march_tiled(int nx, int ny, int fields);
+
 // Geometry of one march, already validated.
 struct Geom {
     int nx, ny, steps;
@@ -45,9 +60,7 @@ Plan plan_carve(void* ws, int nx, int ny);
 // tiled_h: the propagator table in the tiled layout of the two-field march
 hipError_t launch_plan(const Geom& g, const Plan& p, bool with_h, hipStream_t s,
                        bool tiled_h = false);
-// whether `fields` lockstep fields of this geometry take the two-field tiled
-// march (and so need a tiled propagator table)
-bool march_tiled(int nx, int ny, int fields);
+
 
 // Forward march through `steps` slices; field_out doubles as working buffer.
 // Up to kMaxFields fields of one geometry (one plan) march in lockstep in one
@@ -60,8 +73,11 @@ struct MarchIO {
     float* intensity;      // [steps][ny][nx] or nullptr
 };
 // timers: per-workgroup phase timers (diagnostic, see PhaseTimers) or null
+// variant: the kernel (MarchVariant), kMarchAuto to resolve it here; a caller
+// that built the plan for a tiled march passes the variant it resolved then
 hipError_t launch_forward(const Geom& g, const Plan& p, const MarchIO* io, int fields,
-                          hipStream_t s, unsigned long long* timers = nullptr);
+                          hipStream_t s, unsigned long long* timers = nullptr,
+                          int variant = kMarchAuto);
 // words of the phase-timer buffer: a header and one record per workgroup
 constexpr size_t kPhaseTimerWords = 8 + 8 * 4096;
 

@@ -21,6 +21,9 @@
 // column pass multiplies by conj(H).
 #include <hip/hip_runtime.h>
 
+#include <map>
+#include <mutex>
+#include <tuple>
 #include <type_traits>
 
 #include "internal.hpp"
@@ -127,11 +130,55 @@ __global__ void plan_kernel(unsigned* __restrict__ status, float2* __restrict__ 
     }
 }
 
+bool march_variant_eligible(int nx, int ny, int fields, int variant) {
+    const bool sizes = nx >= 32 && ny >= 32 && nx <= 2048 && ny <= 2048 && (nx & (nx - 1)) == 0 &&
+                       (ny & (ny - 1)) == 0 && fields >= 1 && fields <= kMaxFields;
+    if (!sizes) return false;
+    switch (variant) {
+        case kMarchOnePerCu: return true;
+        case kMarchTwoPerCu: return nx >= 512 && ny >= 512;
+        case kMarchTiledPair: {
+            const int cus = device_cus();
+            if (cus <= 0 || 4096 % nx != 0 || 4096 % ny != 0) return false;
+            const int B = 4096 / nx, W = 4096 / ny;  // rows of a row unit, columns of a column unit
+            return fields == 2 && B * W == 16 && cus % 16 == 0 && ny / B == cus && nx / W == cus;
+        }
+        default: return false;
+    }
+}
+
+namespace {
+std::mutex g_variant_mu;
+std::map<std::tuple<int, int, int>, int> g_variant;  // tuned kernel per (nx, ny, fields)
+}  // namespace
+
+int set_march_variant(int nx, int ny, int fields, int variant) {
+    std::lock_guard<std::mutex> lk(g_variant_mu);
+    if (variant == kMarchAuto) {
+        g_variant.erase(std::make_tuple(nx, ny, fields));
+        return 0;
+    }
+    if (!march_variant_eligible(nx, ny, fields, variant)) return -1;
+    g_variant[std::make_tuple(nx, ny, fields)] = variant;
+    return 0;
+}
+
+int march_variant(int nx, int ny, int fields) {
+    {
+        std::lock_guard<std::mutex> lk(g_variant_mu);
+        const auto it = g_variant.find(std::make_tuple(nx, ny, fields));
+        if (it != g_variant.end() && march_variant_eligible(nx, ny, fields, it->second))
+            return it->second;
+    }
+    // built-in choice: the tiled kernel for the two-field geometry it serves,
+    // two workgroups per CU for several fields of sizes >= 512, else one
+    if (march_variant_eligible(nx, ny, fields, kMarchTiledPair)) return kMarchTiledPair;
+    if (fields >= 2 && march_variant_eligible(nx, ny, fields, kMarchTwoPerCu)) return kMarchTwoPerCu;
+    return kMarchOnePerCu;
+}
+
 bool march_tiled(int nx, int ny, int fields) {
-    const int cus = device_cus();
-    if (nx <= 0 || ny <= 0 || 4096 % nx != 0 || 4096 % ny != 0 || cus <= 0) return false;
-    const int B = 4096 / nx, W = 4096 / ny;  // rows of a row unit, columns of a column unit
-    return fields == 2 && B * W == 16 && cus % 16 == 0 && ny / B == cus && nx / W == cus;
+    return march_variant(nx, ny, fields) == kMarchTiledPair;
 }
 
 hipError_t launch_plan(const Geom& g, const Plan& p, bool with_h, hipStream_t s, bool tiled_h) {
@@ -287,7 +334,7 @@ static hipError_t dispatch_nx(int nx, F&& f) {
 }
 
 hipError_t launch_forward(const Geom& g, const Plan& p, const MarchIO* io, int fields,
-                          hipStream_t s, unsigned long long* timers) {
+                          hipStream_t s, unsigned long long* timers, int variant) {
     const size_t plane = (size_t)g.nx * g.ny;
     if (fields < 1 || fields > kMaxFields) return hipErrorInvalidValue;
     if (g.steps == 0) {
@@ -318,6 +365,8 @@ hipError_t launch_forward(const Geom& g, const Plan& p, const MarchIO* io, int f
     a.ny = g.ny;
     a.steps = g.steps;
     a.fields = fields;
+    a.variant = variant == kMarchAuto ? march_variant(g.nx, g.ny, fields) : variant;
+    if (!march_variant_eligible(g.nx, g.ny, fields, a.variant)) return hipErrorInvalidConfiguration;
     a.k0dz = k0dz_of(g);
     return dispatch_nx(g.nx, [&](auto xc) {
         constexpr int NX = decltype(xc)::value;

@@ -48,6 +48,7 @@ struct MarchArgs {
     unsigned limit;    // polls of one barrier wait before it gives up
     unsigned long long* timers;  // phase timers (diagnostic) or null
     int nx, ny, steps, fields;
+    int variant;  // kernel of the march (MarchVariant), resolved on the host
     float k0dz;
 };
 
@@ -443,29 +444,28 @@ hipError_t launch_forward_x(const MarchArgs& a, hipStream_t s) {
     return dispatch_ny(a.ny, [&](auto yc) {
         constexpr int NY = decltype(yc)::value;
         void* args[] = {const_cast<MarchArgs*>(&a)};
-        // two fields whose passes have one unit per CU each: a barrier per field
         const int cus = device_cus();
         if constexpr (units_per_block<NX>() * units_per_block<NY>() == 16) {
-            if (march_tiled(NX, NY, a.fields))
+            if (a.variant == kMarchTiledPair)
                 return hipLaunchCooperativeKernel(
                     reinterpret_cast<const void*>(&march_duo_kernel<NX, NY>), dim3(2 * cus),
                     dim3(kBlock), args,
                     (unsigned)(march_data_lds<NX, NY>() + march_twiddle_lds<NX, NY>()), s);
         }
         if constexpr (NX >= 512 && NY >= 512) {
-            if (a.fields >= 2)
+            if (a.variant == kMarchTwoPerCu)
                 return hipLaunchCooperativeKernel(
                     reinterpret_cast<const void*>(&march_kernel<NX, NY, 2>),
                     dim3(persistent_grid<NX, NY>(a.nx, a.ny, a.fields, 2)), dim3(kBlock), args,
                     (unsigned)(march_data_lds<NX, NY>() + march_twiddle_lds<NX, NY>()), s);
         }
+        if (a.variant != kMarchOnePerCu) return hipErrorInvalidConfiguration;
         return hipLaunchCooperativeKernel(reinterpret_cast<const void*>(&march_kernel<NX, NY, 1>),
                                           dim3(persistent_grid<NX, NY>(a.nx, a.ny, a.fields)),
                                           dim3(kBlock), args, (unsigned)persistent_lds<NX, NY>(),
                                           s);
     });
 }
-
 template <int NX>
 hipError_t launch_adjoint_x(const AdjointArgs& a, hipStream_t s) {
     return dispatch_ny(a.ny, [&](auto yc) {

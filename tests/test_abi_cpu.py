@@ -264,3 +264,26 @@ def test_fallback_runs_keep_sources_apart():
                 d = np.minimum(d, n - d)
                 assert d.max() > sep
     assert fallback_runs(np.zeros((0, 2), int), 64, 64) == []
+
+
+def test_march_variant_choice_and_overrides(L):
+    """Kernel choice of the forward march per shape: eligibility, the
+    built-in choice and overrides (no device: the tiled two-field kernel,
+    which needs the device's CU count, is never eligible here)."""
+    from paper_1706_02261_amd import _lib as B
+    assert L.bpm_march_variant_eligible(64, 64, 1, B.BPM_MARCH_ONE_PER_CU) == 1
+    assert L.bpm_march_variant_eligible(256, 1024, 2, B.BPM_MARCH_TWO_PER_CU) == 0
+    assert L.bpm_march_variant_eligible(512, 1024, 3, B.BPM_MARCH_TWO_PER_CU) == 1
+    assert L.bpm_march_variant_eligible(512, 512, 9, B.BPM_MARCH_ONE_PER_CU) == 0
+    assert L.bpm_march_variant_eligible(512, 512, 1, 7) == 0
+    assert L.bpm_march_variant(100, 64, 1) == B.BPM_ERR_INVALID_ARG
+    assert L.bpm_march_variant(512, 512, 1) == B.BPM_MARCH_ONE_PER_CU
+    assert L.bpm_march_variant(512, 512, 2) == B.BPM_MARCH_TWO_PER_CU
+    assert L.bpm_set_march_variant(512, 512, 2, B.BPM_MARCH_ONE_PER_CU) == B.BPM_OK
+    assert L.bpm_march_variant(512, 512, 2) == B.BPM_MARCH_ONE_PER_CU
+    assert L.bpm_march_variant(512, 512, 3) == B.BPM_MARCH_TWO_PER_CU     # other shape untouched
+    assert L.bpm_set_march_variant(512, 512, 2, B.BPM_MARCH_AUTO) == B.BPM_OK
+    assert L.bpm_march_variant(512, 512, 2) == B.BPM_MARCH_TWO_PER_CU
+    assert L.bpm_set_march_variant(256, 256, 2, B.BPM_MARCH_TWO_PER_CU) == B.BPM_ERR_INVALID_ARG
+    assert L.bpm_set_march_variant(256, 256, 2, 9) == B.BPM_ERR_INVALID_ARG
+    assert L.bpm_set_march_variant(256, 256, 0, B.BPM_MARCH_AUTO) == B.BPM_ERR_INVALID_ARG
