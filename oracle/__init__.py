@@ -13,6 +13,10 @@ Parity status of each function (what pins it, see tests/test_oracle_*.py):
 * bpm_forward     -- dense-matrix recursion on 8x8, Parseval, thin-grating
                      Jacobi-Anger closed form, Gaussian-beam paraxial width,
                      linearity (multiplexing), resume.
+* bpm_forward_adapted -- dn_ref = 0 is bpm_forward; a plane wave through
+                     homogeneous layers expanded about their own index
+                     follows the exact layered-medium phase; modes between
+                     the n0 and the adapted evanescent cut propagate.
 * bpm_adjoint     -- dot-product test, central finite differences, phase
                      conjugation optimum, per-slice gauge invariance.
 * conv3d_*        -- (surrogate) direct definition vs scipy correlate and
@@ -69,6 +73,9 @@ def _declare(L):
     L.oracle_fft2d.argtypes = [_dp, _I, _I, _I]
     L.oracle_propagator.argtypes = [_I, _I, _D, _D, _D, _D, _dp]
     L.oracle_bpm_forward.argtypes = [_dp, _dp, _I, _I, _I, _D, _D, _D, _D, _dp, _dp]
+    L.oracle_bpm_forward_adapted.argtypes = [_dp, _dp, _dp, _I, _I, _I, _D, _D, _D, _D, _dp,
+                                             _dp]
+    L.oracle_bpm_forward_adapted.restype = _I
     L.oracle_bpm_adjoint.argtypes = [_dp, _dp, _I, _I, _I, _D, _D, _D, _D,
                                      _dp, _dp, _dp, _dp, _dp]
     L.oracle_set_threads.argtypes = [_I]
@@ -147,6 +154,24 @@ def bpm_forward(u0, dn, dx, dz, wavelength, n0, intensity=True):
                                   dx, dz, wavelength, n0, _ptr(out.view(np.float64)),
                                   _ptr(inten))
     _check(rc, "bpm_forward")
+    return out, inten
+
+
+def bpm_forward_adapted(u0, dn, dn_ref, dx, dz, wavelength, n0, intensity=True):
+    """March with a per-slice reference index n0 + dn_ref[j] (the locally
+    adapted expansion; see oracle.c).  Returns (u_out, I or None)."""
+    u = _c128(u0)
+    d = _f64(dn)
+    r = _f64(dn_ref)
+    steps, ny, nx = d.shape
+    if r.shape != (steps,):
+        raise ValueError(f"dn_ref has shape {r.shape}, expected ({steps},)")
+    out = np.empty_like(u)
+    inten = np.empty((steps, ny, nx), dtype=np.float64) if intensity else None
+    rc = lib().oracle_bpm_forward_adapted(_ptr(u.view(np.float64)), _ptr(d), _ptr(r), nx, ny,
+                                          steps, dx, dz, wavelength, n0,
+                                          _ptr(out.view(np.float64)), _ptr(inten))
+    _check(rc, "bpm_forward_adapted")
     return out, inten
 
 

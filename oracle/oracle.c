@@ -179,7 +179,9 @@ static int check_geom(int nx, int ny, int steps, double dx, double dz, double la
 }
 
 /* one step u <- S_j * IDFT2(H * DFT2(u)) */
-static int step_forward(cplx *u, const cplx *H, const double *dn_j, int nx, int ny, double k0dz) {
+/* one step; the screen uses dn[j] - ref (ref = 0 in the plain march) */
+static int step_forward_ref(cplx *u, const cplx *H, const double *dn_j, double ref, int nx, int ny,
+                            double k0dz) {
     long n = (long)nx * ny;
     int rc = fft2d(u, nx, ny, -1);
     if (rc) return rc;
@@ -188,10 +190,14 @@ static int step_forward(cplx *u, const cplx *H, const double *dn_j, int nx, int 
     if (rc) return rc;
     double inv = 1.0 / (double)n;
     for (long i = 0; i < n; i++) {
-        double ph = k0dz * dn_j[i];
+        double ph = k0dz * (dn_j[i] - ref);
         u[i] *= inv * (cos(ph) + I * sin(ph));
     }
     return 0;
+}
+
+static int step_forward(cplx *u, const cplx *H, const double *dn_j, int nx, int ny, double k0dz) {
+    return step_forward_ref(u, H, dn_j, 0.0, nx, ny, k0dz);
 }
 
 int oracle_bpm_forward(const double *u0, const double *dn, int nx, int ny, int steps,
@@ -222,6 +228,52 @@ int oracle_bpm_forward(const double *u0, const double *dn, int nx, int ny, int s
 
 /* ------------------------------------------------------------------------ */
 /* adjoint march                                                            */
+
+/*
+ * Locally adapted expansion of the refractive index (main text, paragraph on
+ * the beam-propagation model: the exact propagator is used "together with a
+ * locally adapted expansion of refractive indices"; the details sit in
+ * supplementary notes that are not part of the text).  Reading used here:
+ * slice j is expanded about its own reference index nr_j = n0 + dn_ref[j]
+ * instead of n0.  The step propagates with the exact propagator of a
+ * homogeneous medium of index nr_j, evanescent modes cut at kt^2 <= (nr_j k0)^2
+ * (integer test as prop_mask with nr_j in place of n0), and the screen carries
+ * only the remainder:
+ *
+ *   v       = IDFT2( H_j * DFT2(u_j) ),  H_j = exp(i dz sqrt((nr_j k0)^2 - kt^2))
+ *   u_{j+1} = exp(i k0 dz (dn[j] - dn_ref[j])) * v
+ *   I[j]    = |u_{j+1}|^2
+ *
+ * A slice that is homogeneous at nr_j is then propagated exactly; with
+ * dn_ref = 0 this is oracle_bpm_forward.
+ */
+int oracle_bpm_forward_adapted(const double *u0, const double *dn, const double *dn_ref, int nx,
+                               int ny, int steps, double dx, double dz, double lam, double n0,
+                               double *u_out, double *intensity_out) {
+    int rc = check_geom(nx, ny, steps, dx, dz, lam, n0);
+    if (rc) return rc;
+    if (!u0 || !u_out || (steps > 0 && (!dn || !dn_ref))) return ORACLE_ERR_ARG;
+    for (int j = 0; j < steps; j++)
+        if (!(n0 + dn_ref[j] > 0)) return ORACLE_ERR_ARG;
+    long n = (long)nx * ny;
+    cplx *H = (cplx *)malloc(sizeof(cplx) * (size_t)n);
+    cplx *u = (cplx *)malloc(sizeof(cplx) * (size_t)n);
+    if (!H || !u) { free(H); free(u); return ORACLE_ERR_MEM; }
+    memcpy(u, u0, sizeof(cplx) * (size_t)n);
+    double k0dz = 2.0 * PI / lam * dz;
+    for (int j = 0; j < steps && rc == 0; j++) {
+        oracle_propagator(nx, ny, dx, dz, lam, n0 + dn_ref[j], (double *)H);
+        rc = step_forward_ref(u, H, dn + (long)j * n, dn_ref[j], nx, ny, k0dz);
+        if (intensity_out)
+            for (long i = 0; i < n; i++) {
+                double re = creal(u[i]), im = cimag(u[i]);
+                intensity_out[(long)j * n + i] = re * re + im * im;
+            }
+    }
+    if (rc == 0) memcpy(u_out, u, sizeof(cplx) * (size_t)n);
+    free(H); free(u);
+    return rc;
+}
 
 int oracle_bpm_adjoint(const double *u0, const double *dn, int nx, int ny, int steps,
                        double dx, double dz, double lam, double n0,
