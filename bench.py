@@ -417,6 +417,40 @@ def batch_rate(dev, replays=3):
                          "bytes_per_voxel_step": BYTES_PER_VOXEL_STEP}}
 
 
+def adapted_rate(dev, field, dn, g, reps=3):
+    """The march with a locally adapted expansion (each slice about its mean
+    index) on the detection field of the timed volume: one field, slice means
+    included, 40 B model."""
+    import numpy as np
+    import torch
+    import paper_1706_02261_amd as bpm
+    stream = torch.cuda.current_stream(dev)
+    out = torch.empty_like(field)
+    ws = bpm.workspace(bpm.workspace_size(g.nx, g.ny, g.steps), dev)
+    run = lambda: bpm.propagate_adapted(field, dn, g.dx, g.dz, g.wavelength, g.n0,
+                                        intensity=True, out=out, ws=ws, stream=stream)
+    run()
+    torch.cuda.synchronize(dev)
+    ts = []
+    for _ in range(reps):
+        a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        a.record(stream)
+        run()
+        b.record(stream)
+        torch.cuda.synchronize(dev)
+        ts.append(a.elapsed_time(b))
+    ms = float(np.median(ts))
+    vs = g.nx * g.ny * g.steps
+    gbs = BYTES_PER_VOXEL_STEP * vs / (ms / 1e3) / 1e9
+    torch.cuda.empty_cache()
+    return {"workload": f"adapted expansion (slice-mean reference index), detection field "
+                        f"{g.nx}x{g.ny}, {g.steps} slices, intensity written",
+            "ms": round(ms, 3), "gvoxel_steps_per_s": round(vs / (ms / 1e3) / 1e9, 3),
+            "roofline": {"bound": "hbm", "achieved": round(gbs, 1), "peak": HBM_PEAK_GBS,
+                         "unit": "GB/s", "frac": round(gbs / HBM_PEAK_GBS, 4),
+                         "bytes_per_voxel_step": BYTES_PER_VOXEL_STEP}}
+
+
 def phase_split(jobs, ws, stream, launch_ms):
     """One run of the timed launch with per-workgroup phase timers: mean and
     max over workgroups of each phase, in microseconds per step."""
@@ -588,6 +622,7 @@ def main():
         small = {"128x128x64": synth.config0(), "512x512x512": synth.config1()}
     if not args.no_extra:
         line["workloads"] = workload_rates(dev, small)
+        line["adapted"] = adapted_rate(dev, jobs[0]["field"], jobs[0]["dn"], g)
         line["adjoint"] = adjoint_rate(dev)
         line["uneven_batch"] = batch_rate(dev)
     if not args.no_cpu_baseline:

@@ -93,6 +93,32 @@ int bpm_propagate(const bpm_c64* field_in, const float* dn, int nx, int ny, int 
                   bpm_c64* field_out, float* intensity_out,
                   void* workspace, size_t workspace_bytes, void* hip_stream);
 
+/* Forward march with a locally adapted expansion of the refractive index
+ * (the paper's exact propagator "together with a locally adapted expansion
+ * of refractive indices", main-text paragraph on the method; its details are
+ * not part of the text, the reading here is a per-slice reference index).
+ * Slice j is expanded about nr_j = n0 + dn_ref[j]: the step propagates with
+ * the exact propagator of a homogeneous medium of index nr_j,
+ *     H_j = exp(i dz sqrt((nr_j k0)^2 - kx^2 - ky^2)),  0 where kx^2 + ky^2 > (nr_j k0)^2
+ * (integer test with nr_j for n0), and screens with the remainder,
+ *     u_{j+1} = exp(i k0 dz (dn[j] - dn_ref[j])) . IDFT2(H_j . DFT2(u_j)),
+ * so a slice homogeneous at nr_j is propagated exactly.  dn_ref = 0 gives the
+ * march of bpm_propagate (to rounding: H_j is formed on the fly in FP64 and
+ * turned into an FP32 phasor, not read from a table).
+ *   dn_ref    device float32 [steps], reference index offsets; n0 + dn_ref[j]
+ *             must be > 0 (not checked: values on the device); e.g. the slice
+ *             means of bpm_slice_means.
+ * Other arguments, the workspace (bpm_workspace_size(.., BPM_WS_FORWARD)) and
+ * errors as in bpm_propagate.  One field, one workgroup per CU. */
+int bpm_propagate_adapted(const bpm_c64* field_in, const float* dn, const float* dn_ref, int nx,
+                          int ny, int steps, double dx, double dz, double wavelength, double n0,
+                          bpm_c64* field_out, float* intensity_out, void* workspace,
+                          size_t workspace_bytes, void* hip_stream);
+
+/* dn_ref[j] = mean over slice j of dn ([steps][ny][nx] float32 -> [steps]
+ * float32), summed in FP64 in a fixed order (deterministic). */
+int bpm_slice_means(const float* dn, int nx, int ny, int steps, float* dn_ref, void* hip_stream);
+
 /* One job of an uneven batch (host struct; its pointers are device pointers
  * with the meaning and layout of bpm_propagate's arguments). */
 typedef struct {

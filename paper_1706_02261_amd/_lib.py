@@ -40,6 +40,7 @@ EXPORTS = (
     "bpm_march_phase_times", "bpm_release",
     "bpm_propagate_noalloc", "bpm_noalloc_scratch_bytes",
     "bpm_march_variant", "bpm_march_variant_eligible", "bpm_set_march_variant",
+    "bpm_propagate_adapted", "bpm_slice_means",
 )
 BPM_MARCH_AUTO = 0
 BPM_MARCH_ONE_PER_CU = 1
@@ -127,6 +128,11 @@ def _declare(L):
     L.bpm_psf_readout.argtypes = [_V, _I, _I, _D, _D, _D, _D, _D, _I, _V, _I, _I, _I, _D, _V,
                                   _V, _Z, _V]
     L.bpm_psf_readout.restype = _I
+    L.bpm_propagate_adapted.argtypes = [_V, _V, _V, _I, _I, _I, _D, _D, _D, _D, _V, _V, _V, _Z,
+                                        _V]
+    L.bpm_propagate_adapted.restype = _I
+    L.bpm_slice_means.argtypes = [_V, _I, _I, _I, _V, _V]
+    L.bpm_slice_means.restype = _I
     L.bpm_march_variant.argtypes = [_I, _I, _I]
     L.bpm_march_variant.restype = _I
     L.bpm_march_variant_eligible.argtypes = [_I, _I, _I, _I]

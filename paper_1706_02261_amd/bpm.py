@@ -77,6 +77,48 @@ def propagate(field: torch.Tensor, dn: torch.Tensor, dx: float, dz: float,
     return out, intensity_out
 
 
+def slice_means(dn: torch.Tensor, stream=None) -> torch.Tensor:
+    """Mean of every slice of ``dn`` ([steps][ny][nx] float32) -> [steps]."""
+    _need(dn, "dn", torch.float32)
+    if dn.dim() != 3:
+        raise ValueError("dn must be [steps][ny][nx]")
+    steps, ny, nx = dn.shape
+    out = torch.empty(steps, dtype=torch.float32, device=dn.device)
+    check(lib().bpm_slice_means(_ptr(dn), nx, ny, steps, _ptr(out), _stream_ptr(stream)),
+          "bpm_slice_means")
+    return out
+
+
+def propagate_adapted(field: torch.Tensor, dn: torch.Tensor, dx: float, dz: float,
+                      wavelength: float, n0: float, dn_ref: torch.Tensor | None = None,
+                      intensity: bool = True, out: torch.Tensor | None = None,
+                      ws: torch.Tensor | None = None, stream=None):
+    """March with the locally adapted expansion: slice j about n0 + dn_ref[j]
+    (default: the slice means of ``dn``).  Returns (field_out, intensity or
+    None, dn_ref)."""
+    _need(field, "field", torch.complex64)
+    ny, nx = field.shape
+    _need(dn, "dn", torch.float32)
+    if dn.dim() != 3 or tuple(dn.shape[1:]) != (ny, nx):
+        raise ValueError(f"dn has shape {tuple(dn.shape)}, expected [steps][{ny}][{nx}]")
+    steps = dn.shape[0]
+    if dn_ref is None:
+        dn_ref = slice_means(dn, stream=stream)
+    _need(dn_ref, "dn_ref", torch.float32, (steps,))
+    if out is None:
+        out = torch.empty_like(field)
+    _need(out, "out", torch.complex64, (ny, nx))
+    inten = (torch.empty((steps, ny, nx), dtype=torch.float32, device=field.device)
+             if intensity else None)
+    if ws is None:
+        ws = workspace(workspace_size(nx, ny, steps), field.device)
+    rc = lib().bpm_propagate_adapted(_ptr(field), _ptr(dn), _ptr(dn_ref), nx, ny, steps,
+                                     float(dx), float(dz), float(wavelength), float(n0), _ptr(out),
+                                     _ptr(inten), _ptr(ws), ws.numel(), _stream_ptr(stream))
+    check(rc, "bpm_propagate_adapted")
+    return out, inten, dn_ref
+
+
 def propagate_noalloc(field: torch.Tensor, dn: torch.Tensor, dx: float, dz: float,
                       wavelength: float, n0: float, out: torch.Tensor,
                       intensity_out: torch.Tensor | None = None, stream=None):

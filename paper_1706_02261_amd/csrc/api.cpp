@@ -168,6 +168,44 @@ int bpm_propagate(const bpm_c64* field_in, const float* dn, int nx, int ny, int 
     return device_status(bpm::launch_forward(g, p, &io, 1, s), "forward march");
 }
 
+int bpm_slice_means(const float* dn, int nx, int ny, int steps, float* dn_ref, void* hip_stream) {
+    if (!pow2_in_range(nx) || !pow2_in_range(ny))
+        return fail(BPM_ERR_UNSUPPORTED_SIZE,
+                    "nx=%d ny=%d: sizes must be powers of two in [32, 2048]", nx, ny);
+    if (steps < 0) return fail(BPM_ERR_INVALID_ARG, "steps=%d must be >= 0", steps);
+    if (steps > 0 && (!dn || !dn_ref || !aligned(dn, 4) || !aligned(dn_ref, 4)))
+        return fail(BPM_ERR_INVALID_ARG, "dn and dn_ref must be non-null and 4-byte aligned");
+    return device_status(bpm::launch_slice_means(dn, (long)nx * ny, steps, dn_ref,
+                                                 static_cast<hipStream_t>(hip_stream)),
+                         "slice means");
+}
+
+int bpm_propagate_adapted(const bpm_c64* field_in, const float* dn, const float* dn_ref, int nx,
+                          int ny, int steps, double dx, double dz, double wavelength, double n0,
+                          bpm_c64* field_out, float* intensity_out, void* workspace,
+                          size_t workspace_bytes, void* hip_stream) {
+    int rc = check_geom(nx, ny, steps, dx, dz, wavelength, n0);
+    if (rc) return rc;
+    if ((rc = check_field_ptrs(field_in, dn, steps, field_out))) return rc;
+    if (steps > 0 && (!dn_ref || !aligned(dn_ref, 4)))
+        return fail(BPM_ERR_INVALID_ARG, "dn_ref must be non-null and 4-byte aligned");
+    if (intensity_out && !aligned(intensity_out, 4))
+        return fail(BPM_ERR_INVALID_ARG, "intensity_out must be 4-byte aligned");
+    if ((rc = check_workspace(workspace, workspace_bytes, bpm::plan_bytes(nx, ny)))) return rc;
+    hipStream_t s = static_cast<hipStream_t>(hip_stream);
+    if (steps == 0) {
+        if ((const void*)field_out == (const void*)field_in) return BPM_OK;
+        return device_status(hipMemcpyAsync(field_out, field_in, sizeof(bpm_c64) * (size_t)nx * ny,
+                                            hipMemcpyDeviceToDevice, s),
+                             "copy");
+    }
+    const bpm::Geom g{nx, ny, steps, dx, dz, wavelength, n0};
+    const bpm::Plan p = bpm::plan_carve(workspace, nx, ny);
+    if ((rc = device_status(bpm::launch_plan(g, p, false, s), "plan"))) return rc;
+    return device_status(bpm::launch_adapted(g, p, field_in, dn, dn_ref, field_out, intensity_out, s),
+                         "adapted march");
+}
+
 // ---------------------------------------------------------------------------
 // uneven batch
 

@@ -81,6 +81,13 @@ hipError_t launch_forward(const Geom& g, const Plan& p, const MarchIO* io, int f
 // words of the phase-timer buffer: a header and one record per workgroup
 constexpr size_t kPhaseTimerWords = 8 + 8 * 4096;
 
+// Forward march of one field with a per-slice reference index n0 + dn_ref[j]
+// (locally adapted expansion; the plan needs no propagator table).
+hipError_t launch_adapted(const Geom& g, const Plan& p, const void* field_in, const float* dn,
+                          const float* dn_ref, void* field_out, float* intensity, hipStream_t s);
+// dn_ref[j] = mean of slice j of dn ([steps][plane] float32)
+hipError_t launch_slice_means(const float* dn, long plane, int steps, float* out, hipStream_t s);
+
 // Adjoint march (steps >= 1) with a checkpoint every K steps; `fields` holds
 // adjoint_fields(steps, K) fields of nx * ny complex64.
 struct AdjointIO {

@@ -374,6 +374,62 @@ hipError_t launch_forward(const Geom& g, const Plan& p, const MarchIO* io, int f
     });
 }
 
+hipError_t launch_adapted(const Geom& g, const Plan& p, const void* field_in, const float* dn,
+                          const float* dn_ref, void* field_out, float* intensity, hipStream_t s) {
+    if (device_cus() <= 0) return hipErrorNoDevice;
+    AdaptArgs a{};
+    a.field_in = (const float2*)field_in;
+    a.work = (float2*)field_out;
+    a.dn = dn;
+    a.dn_ref = dn_ref;
+    a.inten = intensity;
+    a.twx = (const float2*)p.twx;
+    a.twy = (const float2*)p.twy;
+    a.permx = (const int*)p.permx;
+    a.permy = (const int*)p.permy;
+    a.counter = (unsigned*)p.counter;
+    a.status = (unsigned*)p.status;
+    a.limit = wait_limit();
+    a.nx = g.nx;
+    a.ny = g.ny;
+    a.steps = g.steps;
+    a.dx = g.dx;
+    a.dz = g.dz;
+    a.lam = g.wavelength;
+    a.n0 = g.n0;
+    a.k0dz = k0dz_of(g);
+    return dispatch_nx(g.nx, [&](auto xc) {
+        constexpr int NX = decltype(xc)::value;
+        return launch_adapted_x<NX>(a, s);
+    });
+}
+
+// mean of every slice of dn: one workgroup per slice, FP64 sums in a fixed
+// order (thread partial sums over a fixed stride, then a tree)
+__global__ __launch_bounds__(256) void slice_mean_kernel(const float* __restrict__ dn, long plane,
+                                                         int steps, float* __restrict__ out) {
+    __shared__ double part[256];
+    for (int j = blockIdx.x; j < steps; j += gridDim.x) {
+        double acc = 0.0;
+        const float* sl = dn + (size_t)j * plane;
+        for (long e = threadIdx.x; e < plane; e += 256) acc += (double)sl[e];
+        part[threadIdx.x] = acc;
+        __syncthreads();
+        for (int h = 128; h > 0; h >>= 1) {
+            if (threadIdx.x < h) part[threadIdx.x] += part[threadIdx.x + h];
+            __syncthreads();
+        }
+        if (threadIdx.x == 0) out[j] = (float)(part[0] / (double)plane);
+        __syncthreads();
+    }
+}
+
+hipError_t launch_slice_means(const float* dn, long plane, int steps, float* out, hipStream_t s) {
+    if (steps <= 0) return hipSuccess;
+    slice_mean_kernel<<<(unsigned)(steps < 4096 ? steps : 4096), 256, 0, s>>>(dn, plane, steps, out);
+    return hipGetLastError();
+}
+
 size_t adjoint_fields(int steps, int K) {
     const int C = (steps + K - 1) / K;
     return (size_t)C + 2 * (size_t)K + 2;

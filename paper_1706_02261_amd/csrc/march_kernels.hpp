@@ -247,6 +247,115 @@ __global__ __launch_bounds__(kBlock, 2) void march_duo_kernel(MarchArgs a) {
 }
 
 // ---------------------------------------------------------------------------
+// march with a locally adapted expansion of the refractive index
+//
+// Slice j is expanded about its own reference index nr_j = n0 + dn_ref[j]:
+// the column pass multiplies by the exact propagator of a homogeneous medium
+// of index nr_j, built on the fly (evanescent cut by the integer test of the
+// plan kernel with nr_j in place of n0, kz in FP64, the phase dz kz turned
+// into a unit phasor in FP32), and the row pass screens with dn - dn_ref[j].
+// One field, one workgroup per CU, twiddles in registers; the propagator
+// values of a column unit are formed before the barrier that guards the field.
+
+struct AdaptArgs {
+    const float2* field_in;
+    float2* work;
+    const float* dn;
+    const float* dn_ref;  // [steps]
+    float* inten;
+    const float2* twx;
+    const float2* twy;
+    const int* permx;
+    const int* permy;
+    unsigned* counter;
+    unsigned* status;
+    unsigned limit;
+    int nx, ny, steps;
+    double dx, dz, lam, n0;
+    float k0dz;
+};
+
+template <int NX, int NY>
+__global__ __launch_bounds__(kBlock, 1) void march_adapted_kernel(AdaptArgs a) {
+    extern __shared__ float2 smem[];
+    const int G = gridDim.x, v = virtual_block();
+    constexpr int B = units_per_block<NX>(), W = units_per_block<NY>(), T = NY / kR;
+    const int rows_u = (a.ny + B - 1) / B, cols_u = (a.nx + W - 1) / W;
+    const size_t plane = (size_t)a.nx * a.ny;
+    unsigned nbar = 0;
+    bool abort = false;
+    Twiddles<NX, kR> twx;
+    Twiddles<NY, kR> twy;
+    twx.load(a.twx, threadIdx.x % (NX / kR));
+    twy.load(a.twy, threadIdx.x / W);
+    float d[kR];
+    for (int i = 0; i < kR; ++i) d[i] = 0.f;
+    for (int u = v; u < rows_u; u += G) {
+        const RowArgs ra{a.field_in, a.work, nullptr, nullptr, nullptr, nullptr, nullptr, a.k0dz};
+        row_unit<NX, kNaturalIn, kNoOps, kSpecOut>(u, a.ny, ra, d, twx, smem);
+    }
+    const double kPi = 3.14159265358979323846;
+    const double k0 = 2.0 * kPi / a.lam;
+    const float scale = (float)(1.0 / ((double)a.nx * (double)a.ny));
+    const int w = threadIdx.x % W, t = threadIdx.x / W;
+    for (int j = 0; j < a.steps; ++j) {
+        const double nr = a.n0 + (double)a.dn_ref[j];
+        const double kj2 = (nr * k0) * (nr * k0);
+        const double ts = (double)a.nx * (double)a.ny * nr * a.dx / a.lam;
+        const double thr = ts * ts;
+        // this step's propagator values of the workgroup's first column unit
+        auto propagator = [&](int u, float2 (&h)[kR]) {
+            const int c = u * W + w;
+            const int m = a.permx[c < a.nx ? c : 0];
+            const long ms = m < a.nx / 2 ? m : m - a.nx;
+            const double kx = 2.0 * kPi * (double)ms / (a.nx * a.dx);
+            const double a2 = (double)(ms * a.ny) * (double)(ms * a.ny);
+#pragma unroll
+            for (int r = 0; r < kR; ++r) {
+                const int l = a.permy[r * T + t];
+                const long ls = l < a.ny / 2 ? l : l - a.ny;
+                const double ky = 2.0 * kPi * (double)ls / (a.ny * a.dx);
+                const double b2 = (double)(ls * a.nx) * (double)(ls * a.nx);
+                float2 hv = make_float2(0.f, 0.f);
+                if (a2 + b2 <= thr) {
+                    const double kz = sqrt(fmax(kj2 - kx * kx - ky * ky, 0.0));
+                    const float2 e = expi((float)(a.dz * kz));
+                    hv = make_float2(e.x * scale, e.y * scale);
+                }
+                h[r] = hv;
+            }
+        };
+        float2 h[kR];
+        propagator(v, h);
+        grid_sync(a.counter, ++nbar, abort, a.status, a.limit);
+        for (int u = v; u < cols_u; u += G) {
+            if (u != v) propagator(u, h);
+            float2 vals[kR];
+            const int c = u * W + w;
+            const size_t col = c < a.nx ? (size_t)c : 0;
+#pragma unroll
+            for (int i = 0; i < kR; ++i) vals[i] = ld_shared_field(a.work + (size_t)(i * T + t) * a.nx + col);
+            col_body<NY, false>(u, a.nx, a.work, twy, smem, nullptr, nullptr, nullptr, vals, h);
+        }
+        grid_sync(a.counter, ++nbar, abort, a.status, a.limit);
+        const float ref = a.dn_ref[j];
+        for (int u = v; u < rows_u; u += G) {
+            float2 vals[kR];
+            row_load<NX, kSpecIn>(u, a.ny, a.work, vals);
+            load_dn<NX>(d, u, a.ny, a.dn + (size_t)j * plane);
+#pragma unroll
+            for (int i = 0; i < kR; ++i) d[i] -= ref;
+            const RowArgs ra{a.work, a.work, a.inten ? a.inten + (size_t)j * plane : nullptr,
+                             nullptr, nullptr, nullptr, nullptr, a.k0dz};
+            if (j + 1 < a.steps)
+                row_body<NX, kSpecIn, kScreen, kSpecOut>(u, a.ny, ra, d, twx, smem, vals);
+            else
+                row_body<NX, kSpecIn, kScreen, kNaturalOut>(u, a.ny, ra, d, twx, smem, vals);
+        }
+    }
+}
+
+// ---------------------------------------------------------------------------
 // persistent adjoint march with checkpointing
 //
 //   1. forward march from u_0 keeping u at every K-th slice boundary;
@@ -481,12 +590,26 @@ hipError_t launch_adjoint_x(const AdjointArgs& a, hipStream_t s) {
 
 static_assert(kPhaseTimerWords == kPhaseWords * (kMaxTimedGroups + 1), "timer layout");
 
+template <int NX>
+hipError_t launch_adapted_x(const AdaptArgs& a, hipStream_t s) {
+    return dispatch_ny(a.ny, [&](auto yc) {
+        constexpr int NY = decltype(yc)::value;
+        void* args[] = {const_cast<AdaptArgs*>(&a)};
+        return hipLaunchCooperativeKernel(
+            reinterpret_cast<const void*>(&march_adapted_kernel<NX, NY>),
+            dim3(persistent_grid<NX, NY>(a.nx, a.ny, 1)), dim3(kBlock), args,
+            (unsigned)persistent_lds<NX, NY>(), s);
+    });
+}
+
 // one translation unit per row length
 #define BPM_MARCH_INSTANTIATE(NX)                                                  \
     template hipError_t launch_forward_x<NX>(const MarchArgs&, hipStream_t);      \
-    template hipError_t launch_adjoint_x<NX>(const AdjointArgs&, hipStream_t);
+    template hipError_t launch_adjoint_x<NX>(const AdjointArgs&, hipStream_t);    \
+    template hipError_t launch_adapted_x<NX>(const AdaptArgs&, hipStream_t);
 #define BPM_MARCH_EXTERN(NX)                                                       \
     extern template hipError_t launch_forward_x<NX>(const MarchArgs&, hipStream_t); \
-    extern template hipError_t launch_adjoint_x<NX>(const AdjointArgs&, hipStream_t);
+    extern template hipError_t launch_adjoint_x<NX>(const AdjointArgs&, hipStream_t); \
+    extern template hipError_t launch_adapted_x<NX>(const AdaptArgs&, hipStream_t);
 
 }  // namespace bpm

@@ -287,3 +287,18 @@ def test_march_variant_choice_and_overrides(L):
     assert L.bpm_set_march_variant(256, 256, 2, B.BPM_MARCH_TWO_PER_CU) == B.BPM_ERR_INVALID_ARG
     assert L.bpm_set_march_variant(256, 256, 2, 9) == B.BPM_ERR_INVALID_ARG
     assert L.bpm_set_march_variant(256, 256, 0, B.BPM_MARCH_AUTO) == B.BPM_ERR_INVALID_ARG
+
+
+def test_adapted_march_validation(L):
+    from paper_1706_02261_amd import _lib as B
+    b = Buf()
+    ws = L.bpm_workspace_size(64, 64, 2, 0)
+    assert L.bpm_propagate_adapted(b.p, b.p, None, 64, 64, 2, 0.2, 0.2, 0.5, 1.33, b.p, None,
+                                   b.p, ws, None) == B.BPM_ERR_INVALID_ARG
+    assert L.bpm_propagate_adapted(b.p, b.p, b.p, 100, 64, 2, 0.2, 0.2, 0.5, 1.33, b.p, None,
+                                   b.p, ws, None) == B.BPM_ERR_UNSUPPORTED_SIZE
+    assert L.bpm_propagate_adapted(b.p, b.p, b.p, 64, 64, 2, 0.2, 0.2, 0.5, 1.33, b.p, None,
+                                   b.p, 16, None) == B.BPM_ERR_WORKSPACE
+    assert L.bpm_slice_means(b.p, 64, 64, -1, b.p, None) == B.BPM_ERR_INVALID_ARG
+    assert L.bpm_slice_means(None, 64, 64, 3, b.p, None) == B.BPM_ERR_INVALID_ARG
+    assert L.bpm_slice_means(b.p, 64, 48, 3, b.p, None) == B.BPM_ERR_UNSUPPORTED_SIZE
