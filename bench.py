@@ -451,6 +451,77 @@ def adapted_rate(dev, field, dn, g, reps=3):
                          "bytes_per_voxel_step": BYTES_PER_VOXEL_STEP}}
 
 
+def ao_rates(dev, reps=5):
+    """Adaptive optics on the Perlin tissue (256^2 x 80, n = 1.36 +- 0.03):
+    guide-star correction latency (linear adjoint + phase kernel), focus
+    intensities (clear, aimed, corrected; fraction of the optimum), one Adam
+    iteration of the pupil optimiser, a 12-shift memory-effect sweep, and the
+    same correction through the 256^2 x 512 adjoint workload."""
+    import numpy as np
+    import torch
+    import synth
+    from paper_1706_02261_amd import ao
+
+    def timed(fn):
+        fn()
+        torch.cuda.synchronize(dev)
+        ts = []
+        for _ in range(reps):
+            a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            a.record()
+            fn()
+            b.record()
+            torch.cuda.synchronize(dev)
+            ts.append(a.elapsed_time(b))
+        return float(np.median(ts))
+
+    g, dn, amp, zf = synth.ao_workload(256, 80)
+    opt = ao.Optics(g.dx, g.dz, g.wavelength, g.n0)
+    f = (g.ny // 2, g.nx // 2)
+    dn_t = torch.from_numpy(dn).to(dev)
+    amp_t = torch.from_numpy(amp).to(dev)
+    phi, gs = ao.guide_star_phase(dn_t, f, zf, opt)
+    aim = ao.aim_phase(g.ny, g.nx, f, opt, device=dev)
+    at = lambda ph, d: float(ao.exit_field(amp_t, ph, d, zf, opt)[f].abs() ** 2)
+    corr, unc, clear = at(phi, dn_t), at(aim, dn_t), at(aim, torch.zeros_like(dn_t))
+    best = ao.optimum_intensity(amp_t, gs)
+    ms_gs = timed(lambda: ao.guide_star_phase(dn_t, f, zf, opt))
+    prob = ao._FocusProblem(dn_t, [f])
+    ms_it = timed(lambda: prob.gradient(amp_t, aim, dn_t, zf, opt))
+    shifts = [(0, s) for s in range(1, 7)] + [(s, 0) for s in range(1, 7)]
+    ms_me = timed(lambda: ao.memory_effect(amp_t, gs, dn_t, f, shifts, zf, opt))
+    P, _ = ao.memory_effect(amp_t, gs, dn_t, f, shifts, zf, opt)
+    pw = ao.plane_wave_exit(dn_t, opt)
+    C = ao.speckle_autocorrelation((pw.abs() ** 2).contiguous(), 6)
+
+    def half_width(c):
+        for i in range(1, len(c)):
+            if c[i] < 0.5:
+                return i - 1 + (c[i - 1] - 0.5) / (c[i - 1] - c[i])
+        return None
+    Pm = np.r_[1.0, 0.5 * (P[:6] + P[6:])]
+    g3, dn3, _, _ = synth.config3()
+    dn3_t = torch.from_numpy(dn3).to(dev)
+    ms_gs3 = timed(lambda: ao.guide_star_phase(dn3_t, (g3.ny // 2, g3.nx // 2),
+                                               g3.steps * g3.dz, ao.Optics(g3.dx, g3.dz,
+                                                                           g3.wavelength, g3.n0)))
+    del dn_t, dn3_t, prob
+    torch.cuda.empty_cache()
+    return {"workload": "Perlin tissue 256x256x80 (dx = dz = 0.2 um, n = 1.36 +- 0.03 as a "
+                        "standard deviation), NA 0.6 Gaussian pupil, focus at the exit plane",
+            "mean_free_paths": round(ao.mean_free_paths(pw), 3),
+            "focus_intensity": {"clear": clear, "aimed": unc, "corrected": corr,
+                                "corrected_over_optimum": round(corr / best, 6),
+                                "corrected_over_clear": round(corr / clear, 4),
+                                "enhancement_over_aimed": round(corr / unc, 3)},
+            "guide_star_ms": round(ms_gs, 4),
+            "optimizer_iteration_ms": round(ms_it, 4),
+            "memory_effect_sweep_ms": round(ms_me, 3), "memory_effect_shifts": len(shifts),
+            "persistence_half_width_px": half_width(Pm),
+            "speckle_half_width_px": half_width(C),
+            "guide_star_ms_256x256x512": round(ms_gs3, 4)}
+
+
 def phase_split(jobs, ws, stream, launch_ms):
     """One run of the timed launch with per-workgroup phase timers: mean and
     max over workgroups of each phase, in microseconds per step."""
@@ -624,6 +695,7 @@ def main():
         line["workloads"] = workload_rates(dev, small)
         line["adapted"] = adapted_rate(dev, jobs[0]["field"], jobs[0]["dn"], g)
         line["adjoint"] = adjoint_rate(dev)
+        line["adaptive_optics"] = ao_rates(dev)
         line["uneven_batch"] = batch_rate(dev)
     if not args.no_cpu_baseline:
         def gpu_first(steps):

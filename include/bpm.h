@@ -207,7 +207,11 @@ size_t bpm_adjoint_workspace_size(int nx, int ny, int steps, int checkpoint_ever
  *   grad_dn          [steps][ny][nx] receives dL/ddn, or NULL.
  *   checkpoint_every 0 (= ceil(sqrt(steps))) or 1 .. steps.
  * Other arguments as in bpm_propagate.  Results do not depend on
- * checkpoint_every (bitwise). */
+ * checkpoint_every (bitwise).  With grad_intensity and grad_dn both NULL the
+ * adjoint is the linear map M^H applied to grad_field_out (for a point at a
+ * focus: the guide star's field conjugated back to the entrance plane); the
+ * call then skips the forward march and field_in may be NULL; otherwise a
+ * NULL field_in is BPM_ERR_INVALID_ARG. */
 int bpm_adjoint(const bpm_c64* field_in, const float* dn, int nx, int ny, int steps,
                 double dx, double dz, double wavelength, double n0,
                 const bpm_c64* grad_field_out, const float* grad_intensity,
@@ -240,6 +244,32 @@ int bpm_pupil_spectrum(const float* amplitude, const float* phase, int nx, int n
  * spectrum U0 of bpm_pupil_spectrum ([ny][nx] each; grad_phase float32). */
 int bpm_pupil_phase_grad(const bpm_c64* grad_spectrum, const bpm_c64* spectrum, int nx, int ny,
                          float* grad_phase, void* hip_stream);
+
+/* Guide-star correction (main-text paragraph on adaptive optics: conjugating
+ * the wavefront of a point-like guide star at the sample surface gives a
+ * diffraction-limited focus inside scattering tissue).  grad_spectrum is
+ * G = dL/dU0 of bpm_adjoint with grad_field_out a point at the focus and no
+ * other gradient (G = DFT2(M^H e_f) / (nx ny)).  The focus amplitude
+ * u(x_f) = sum conj(G) U0 is largest over |U0| = A when every mode of
+ * U0 = A exp(i phi) exp(-i kz z_focus) has the phase of G, so the call writes
+ *     phase_out = arg G + kz z_focus - kx shift_x - ky shift_y   in [-pi, pi),
+ * kx, ky, kz on the natural DFT grid as in bpm_pupil_spectrum.  A nonzero
+ * (shift_x, shift_y) (micrometres) moves the corrected entrance field by that
+ * vector (the shifted correction of a memory-effect measurement).  Arrays
+ * [ny][nx]: grad_spectrum complex64, phase_out float32. */
+int bpm_guide_star_phase(const bpm_c64* grad_spectrum, int nx, int ny, double dx,
+                         double wavelength, double n0, double z_focus, double shift_x,
+                         double shift_y, float* phase_out, void* hip_stream);
+
+/* One Adam update (Kingma & Ba 2015, Algorithm 1: beta1 0.9, beta2 0.999,
+ * eps 1e-8) of n float32 parameters in place, with the moments m and v
+ * (zero before step 1) updated in place and 1-based step `step` for the bias
+ * corrections:  m = b1 m + (1-b1) g,  v = b2 v + (1-b2) g^2,
+ * params -= lr (m / (1 - b1^step)) / (sqrt(v / (1 - b2^step)) + eps).
+ * The optimiser of the adaptive-optics pupil phase; the same kernel updates
+ * the PSF surrogate.  Device arrays, 4-byte aligned. */
+int bpm_adam_step(float* params, const float* grads, float* m, float* v, long n, float lr,
+                  int step, void* hip_stream);
 
 /* Bytes of workspace for bpm_psf_readout. */
 size_t bpm_psf_readout_workspace_size(int nx, int ny, int planes);

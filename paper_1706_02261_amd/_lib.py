@@ -41,6 +41,7 @@ EXPORTS = (
     "bpm_propagate_noalloc", "bpm_noalloc_scratch_bytes",
     "bpm_march_variant", "bpm_march_variant_eligible", "bpm_set_march_variant",
     "bpm_propagate_adapted", "bpm_slice_means",
+    "bpm_guide_star_phase", "bpm_adam_step",
 )
 BPM_MARCH_AUTO = 0
 BPM_MARCH_ONE_PER_CU = 1
@@ -123,6 +124,10 @@ def _declare(L):
     L.bpm_pupil_spectrum.restype = _I
     L.bpm_pupil_phase_grad.argtypes = [_V, _V, _I, _I, _V, _V]
     L.bpm_pupil_phase_grad.restype = _I
+    L.bpm_guide_star_phase.argtypes = [_V, _I, _I, _D, _D, _D, _D, _D, _D, _V, _V]
+    L.bpm_guide_star_phase.restype = _I
+    L.bpm_adam_step.argtypes = [_V, _V, _V, _V, ctypes.c_long, ctypes.c_float, _I, _V]
+    L.bpm_adam_step.restype = _I
     L.bpm_psf_readout_workspace_size.argtypes = [_I, _I, _I]
     L.bpm_psf_readout_workspace_size.restype = _Z
     L.bpm_psf_readout.argtypes = [_V, _I, _I, _D, _D, _D, _D, _D, _I, _V, _I, _I, _I, _D, _V,

@@ -172,10 +172,18 @@ def adjoint(field: torch.Tensor, dn: torch.Tensor, dx: float, dz: float, wavelen
     """Gradients through ``propagate`` (PyTorch's complex convention).
 
     Returns ``(grad_field_in, grad_spectrum_in, grad_dn)`` with None for the
-    ones not requested."""
-    _need(field, "field", torch.complex64)
-    ny, nx = field.shape
+    ones not requested.  ``field`` may be None when neither intensity nor dn
+    gradients are wanted (``grad_intensity`` None, ``want_dn`` False): the
+    result is then M^H grad_field_out and the forward march is skipped."""
     _need(dn, "dn", torch.float32)
+    if field is None:
+        if grad_field_out is None or grad_intensity is not None or want_dn:
+            raise ValueError("field may be None only for the linear adjoint "
+                             "(grad_field_out given, no grad_intensity, want_dn False)")
+        ny, nx = grad_field_out.shape
+    else:
+        _need(field, "field", torch.complex64)
+        ny, nx = field.shape
     if dn.dim() != 3 or tuple(dn.shape[1:]) != (ny, nx):
         raise ValueError(f"dn has shape {tuple(dn.shape)}, expected [steps][{ny}][{nx}]")
     steps = dn.shape[0]
@@ -183,9 +191,9 @@ def adjoint(field: torch.Tensor, dn: torch.Tensor, dx: float, dz: float, wavelen
         _need(grad_field_out, "grad_field_out", torch.complex64, (ny, nx))
     if grad_intensity is not None:
         _need(grad_intensity, "grad_intensity", torch.float32, (steps, ny, nx))
-    dev = field.device
-    g0 = torch.empty_like(field) if want_field else None
-    gs = torch.empty_like(field) if want_spectrum else None
+    dev = dn.device
+    g0 = torch.empty((ny, nx), dtype=torch.complex64, device=dev) if want_field else None
+    gs = torch.empty((ny, nx), dtype=torch.complex64, device=dev) if want_spectrum else None
     gdn = torch.empty((steps, ny, nx), dtype=torch.float32, device=dev) if want_dn else None
     need = adjoint_workspace_size(nx, ny, steps, checkpoint_every)
     if ws is None:
@@ -224,6 +232,36 @@ def pupil_spectrum(amplitude: torch.Tensor, phase: torch.Tensor, dx: float, wave
                                   _stream_ptr(stream))
     check(rc, "bpm_pupil_spectrum")
     return out
+
+
+def guide_star_phase(grad_spectrum: torch.Tensor, dx: float, wavelength: float, n0: float,
+                     z_focus: float, shift=(0.0, 0.0), out: torch.Tensor | None = None,
+                     stream=None) -> torch.Tensor:
+    """Pupil phase arg(G) + kz z_focus - kx shift_x - ky shift_y in [-pi, pi)
+    from the spectrum gradient G of a point at the focus (``shift`` = (x, y)
+    in micrometres moves the corrected entrance field)."""
+    _need(grad_spectrum, "grad_spectrum", torch.complex64)
+    ny, nx = grad_spectrum.shape
+    if out is None:
+        out = torch.empty((ny, nx), dtype=torch.float32, device=grad_spectrum.device)
+    _need(out, "out", torch.float32, (ny, nx))
+    rc = lib().bpm_guide_star_phase(_ptr(grad_spectrum), nx, ny, float(dx), float(wavelength),
+                                    float(n0), float(z_focus), float(shift[0]), float(shift[1]),
+                                    _ptr(out), _stream_ptr(stream))
+    check(rc, "bpm_guide_star_phase")
+    return out
+
+
+def adam_step(params: torch.Tensor, grads: torch.Tensor, m: torch.Tensor, v: torch.Tensor,
+              lr: float, step: int, stream=None) -> None:
+    """One Adam update of float32 ``params`` in place (moments m, v in place;
+    1-based ``step``)."""
+    _need(params, "params", torch.float32)
+    for t, name in ((grads, "grads"), (m, "m"), (v, "v")):
+        _need(t, name, torch.float32, tuple(params.shape))
+    rc = lib().bpm_adam_step(_ptr(params), _ptr(grads), _ptr(m), _ptr(v), params.numel(),
+                             float(lr), int(step), _stream_ptr(stream))
+    check(rc, "bpm_adam_step")
 
 
 def pupil_phase_grad(grad_spectrum: torch.Tensor, spectrum: torch.Tensor, stream=None):

@@ -548,7 +548,9 @@ int bpm_adjoint(const bpm_c64* field_in, const float* dn, int nx, int ny, int st
                 void* hip_stream) {
     int rc = check_geom(nx, ny, steps, dx, dz, wavelength, n0);
     if (rc) return rc;
-    if (!field_in) return fail(BPM_ERR_INVALID_ARG, "field_in must be non-null");
+    if (!field_in && (grad_intensity || grad_dn))
+        return fail(BPM_ERR_INVALID_ARG,
+                    "field_in must be non-null when grad_intensity or grad_dn is given");
     if (steps > 0 && !dn) return fail(BPM_ERR_INVALID_ARG, "dn must be non-null when steps > 0");
     if (checkpoint_every < 0 || (steps > 0 && checkpoint_every > steps))
         return fail(BPM_ERR_INVALID_ARG, "checkpoint_every=%d must be 0 or in [1, steps=%d]",
@@ -643,6 +645,39 @@ int bpm_pupil_phase_grad(const bpm_c64* grad_spectrum, const bpm_c64* spectrum, 
     return device_status(bpm::launch_pupil_grad(grad_spectrum, spectrum, (long)nx * ny,
                                                 grad_phase, static_cast<hipStream_t>(hip_stream)),
                          "pupil phase gradient");
+}
+
+int bpm_guide_star_phase(const bpm_c64* grad_spectrum, int nx, int ny, double dx,
+                         double wavelength, double n0, double z_focus, double shift_x,
+                         double shift_y, float* phase_out, void* hip_stream) {
+    int rc = check_geom(nx, ny, 0, dx, 0.0, wavelength, n0);
+    if (rc) return rc;
+    if (!std::isfinite(z_focus) || !std::isfinite(shift_x) || !std::isfinite(shift_y))
+        return fail(BPM_ERR_NOT_FINITE, "z_focus, shift_x and shift_y must be finite");
+    if (!grad_spectrum || !phase_out)
+        return fail(BPM_ERR_INVALID_ARG, "grad_spectrum and phase_out must be non-null");
+    if (!aligned(grad_spectrum, 8) || !aligned(phase_out, 4))
+        return fail(BPM_ERR_INVALID_ARG, "misaligned array");
+    const bpm::Geom g{nx, ny, 0, dx, 0.0, wavelength, n0};
+    return device_status(bpm::launch_guide_star_phase(grad_spectrum, g, z_focus, shift_x, shift_y,
+                                                      phase_out,
+                                                      static_cast<hipStream_t>(hip_stream)),
+                         "guide-star phase");
+}
+
+int bpm_adam_step(float* params, const float* grads, float* m, float* v, long n, float lr,
+                  int step, void* hip_stream) {
+    if (n < 0) return fail(BPM_ERR_INVALID_ARG, "n=%ld must be >= 0", n);
+    if (step < 1) return fail(BPM_ERR_INVALID_ARG, "step=%d must be >= 1", step);
+    if (!std::isfinite(lr)) return fail(BPM_ERR_NOT_FINITE, "lr must be finite");
+    if (n == 0) return BPM_OK;
+    if (!params || !grads || !m || !v)
+        return fail(BPM_ERR_INVALID_ARG, "params, grads, m and v must be non-null");
+    if (!aligned(params, 4) || !aligned(grads, 4) || !aligned(m, 4) || !aligned(v, 4))
+        return fail(BPM_ERR_INVALID_ARG, "misaligned array");
+    return device_status(bpm::sg::adam_update(params, grads, m, v, n, lr, step,
+                                         static_cast<hipStream_t>(hip_stream)),
+                         "Adam step");
 }
 
 size_t bpm_psf_readout_workspace_size(int nx, int ny, int planes) {

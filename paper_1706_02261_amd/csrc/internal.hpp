@@ -213,5 +213,7 @@ hipError_t fill_zero(float* p, long n, hipStream_t s);
 hipError_t launch_pupil_spectrum(const float* amp, const float* phase, const Geom& g, double z_f,
                                  void* U, hipStream_t s);
 hipError_t launch_pupil_grad(const void* G, const void* U, long n, float* gphi, hipStream_t s);
+hipError_t launch_guide_star_phase(const void* G, const Geom& g, double z_f, double sx, double sy,
+                                   float* phase, hipStream_t s);
 
 }  // namespace bpm

@@ -282,6 +282,28 @@ __global__ void pupil_grad_kernel(const float2* __restrict__ G, const float2* __
     }
 }
 
+// Guide-star correction: the pupil phase that puts U0 = A exp(i phi) exp(-i kz z_f)
+// in phase with G = dL/dU0 of a point at the focus, phi = arg G + kz z_f, with
+// the lateral shift (sx, sy) of the corrected field applied as the tilt
+// -(kx sx + ky sy); wrapped to [-pi, pi).
+__global__ void guide_star_phase_kernel(const float2* __restrict__ G, int nx, int ny, double dx,
+                                        double k, double z_f, double sx, double sy,
+                                        float* __restrict__ phase) {
+    const double kPi = 3.14159265358979323846;
+    const long n = (long)nx * ny;
+    for (long e = blockIdx.x * (long)blockDim.x + threadIdx.x; e < n;
+         e += (long)gridDim.x * blockDim.x) {
+        const int l = (int)(e / nx), m = (int)(e % nx);
+        const double kx = 2.0 * kPi * (double)(m < nx / 2 ? m : m - nx) / (nx * dx);
+        const double ky = 2.0 * kPi * (double)(l < ny / 2 ? l : l - ny) / (ny * dx);
+        const double kz = sqrt(fmax(k * k - kx * kx - ky * ky, 0.0));
+        const float2 g = G[e];
+        double p = atan2((double)g.y, (double)g.x) + kz * z_f - kx * sx - ky * sy;
+        p -= 2.0 * kPi * floor((p + kPi) / (2.0 * kPi));
+        phase[e] = (float)p;
+    }
+}
+
 // ---------------------------------------------------------------------------
 // launchers
 
@@ -474,6 +496,16 @@ hipError_t launch_pupil_spectrum(const float* amp, const float* phase, const Geo
     const double k = 2.0 * 3.14159265358979323846 / g.wavelength * g.n0;
     pupil_spectrum_kernel<<<(unsigned)(blocks < 4096 ? blocks : 4096), 256, 0, s>>>(
         amp, phase, g.nx, g.ny, g.dx, k, z_f, (float2*)U);
+    return hipGetLastError();
+}
+
+hipError_t launch_guide_star_phase(const void* G, const Geom& g, double z_f, double sx, double sy,
+                                   float* phase, hipStream_t s) {
+    const long n = (long)g.nx * g.ny;
+    const long blocks = (n + 255) / 256;
+    const double k = 2.0 * 3.14159265358979323846 / g.wavelength * g.n0;
+    guide_star_phase_kernel<<<(unsigned)(blocks < 4096 ? blocks : 4096), 256, 0, s>>>(
+        (const float2*)G, g.nx, g.ny, g.dx, k, z_f, sx, sy, phase);
     return hipGetLastError();
 }
 

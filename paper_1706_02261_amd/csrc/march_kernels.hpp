@@ -422,8 +422,13 @@ __global__ __launch_bounds__(BLK) void adjoint_kernel(AdjointArgs a) {
         }
     };
 
+    // Without intensity and dn gradients the adjoint is the linear map M^H
+    // applied to gout: the adjoint steps read no forward field, so the
+    // checkpoint march and the segment recomputes are skipped.
+    const bool linear = !a.gI && !a.gdn;
+
     // 1. checkpoints u_K, u_2K, ..., u_(C-1)K
-    if (C > 1) {
+    if (C > 1 && !linear) {
         RowArgs ra{a.field_in, a.fwork, nullptr, nullptr, nullptr, nullptr, nullptr, a.k0dz};
         for (int u = v; u < rows_u; u += G)
             row_unit<NX, kNaturalIn, kNoOps, kSpecOut, BLK>(u, a.ny, ra, d, twx, smem);
@@ -496,12 +501,14 @@ __global__ __launch_bounds__(BLK) void adjoint_kernel(AdjointArgs a) {
         }
     };
     // the last segment's recompute alone, then adjoint c with recompute c - 1
-    for (int i = 0; i < 2 * len_of(C - 1) + 1; ++i) {
-        grid_sync(a.counter, ++nbar, abort, a.status, a.limit);
-        for (int u = v; u < rec_units(i); u += G) rec_unit(C - 1, i, u);
+    if (!linear) {
+        for (int i = 0; i < 2 * len_of(C - 1) + 1; ++i) {
+            grid_sync(a.counter, ++nbar, abort, a.status, a.limit);
+            for (int u = v; u < rec_units(i); u += G) rec_unit(C - 1, i, u);
+        }
     }
     for (int c = C - 1; c >= 0; --c) {
-        const int PA = 2 * len_of(c), PR = c > 0 ? 2 * len_of(c - 1) + 1 : 0;
+        const int PA = 2 * len_of(c), PR = c > 0 && !linear ? 2 * len_of(c - 1) + 1 : 0;
         for (int i = 0; i < (PA > PR ? PA : PR); ++i) {
             grid_sync(a.counter, ++nbar, abort, a.status, a.limit);
             const int na = i < PA ? adj_units(i) : 0, nr = i < PR ? rec_units(i) : 0;

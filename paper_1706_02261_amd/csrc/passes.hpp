@@ -114,7 +114,7 @@ struct RowArgs {
     float2* dst;        // spectrum (working buffer) or natural field
     float* inten;       // forward: I slice, or null
     float2* keep;       // forward: copy of the natural u_{j+1}, or null
-    const float2* u;    // adjoint: natural u_{j+1}
+    const float2* u;    // adjoint: natural u_{j+1} (read only when gI or gdn is set)
     const float* gI;    // adjoint: dL/dI slice, or null
     float* gdn;         // adjoint: dL/ddn slice, or null
     float k0dz;
@@ -171,8 +171,10 @@ __device__ __forceinline__ void row_body(int unit, int ny, const RowArgs& a,
         }
     } else if constexpr (OPS == kAdjointOps) {
         float2 u[kR];
+        if (a.gI || a.gdn) {
 #pragma unroll
-        for (int i = 0; i < kR; ++i) u[i] = ld_shared_field(a.u + rowoff + i * T + tau);
+            for (int i = 0; i < kR; ++i) u[i] = ld_shared_field(a.u + rowoff + i * T + tau);
+        }
         if (a.gI) {
 #pragma unroll
             for (int i = 0; i < kR; ++i) {

@@ -296,6 +296,92 @@ def light_sheet_field(nx: int, ny: int, dx: float, wavelength: float, n0: float,
 
 
 # ---------------------------------------------------------------------------
+# Perlin gradient noise (the adaptive-optics phantom)
+
+_GRAD12 = np.array([[1, 1, 0], [-1, 1, 0], [1, -1, 0], [-1, -1, 0], [1, 0, 1], [-1, 0, 1],
+                    [1, 0, -1], [-1, 0, -1], [0, 1, 1], [0, -1, 1], [0, 1, -1], [0, -1, -1]],
+                   dtype=np.float64)
+
+
+def perlin_noise(shape, cell_vox: float, gen: np.random.Generator) -> np.ndarray:
+    """3-D gradient noise on a [nz][ny][nx] grid (Perlin's improved noise:
+    gradients from the 12 cube-edge directions chosen by a hashed permutation
+    of the lattice, quintic fade 6t^5 - 15t^4 + 10t^3, trilinear blend),
+    lattice spacing `cell_vox` voxels.  Values lie in about [-1, 1]."""
+    perm = gen.permutation(256)
+    perm = np.concatenate([perm, perm])
+    nz, ny, nx = shape
+    axes = [np.arange(n, dtype=np.float64) / cell_vox for n in (nz, ny, nx)]
+    out = np.empty(shape, dtype=np.float64)
+    x = axes[2][None, :]
+    xi = np.floor(x).astype(np.int64)
+    xf = x - xi
+    y = axes[1][:, None]
+    yi = np.floor(y).astype(np.int64)
+    yf = y - yi
+    fade = lambda t: t * t * t * (t * (t * 6 - 15) + 10)
+    u, v = fade(xf), fade(yf)
+
+    def grad(h, dx_, dy_, dz_):
+        g = _GRAD12[h % 12]
+        return g[..., 0] * dx_ + g[..., 1] * dy_ + g[..., 2] * dz_
+
+    for k in range(nz):
+        z = axes[0][k]
+        zi = int(np.floor(z))
+        zf = z - zi
+        w = fade(zf)
+        acc = []
+        for cz in (0, 1):
+            for cy in (0, 1):
+                for cx in (0, 1):
+                    h = perm[(perm[(perm[(xi + cx) & 255] + ((yi + cy) & 255)) & 511]
+                              + ((zi + cz) & 255)) & 511]
+                    acc.append(grad(h, xf - cx, yf - cy, zf - cz))
+        lerp = lambda a, b, t: a + t * (b - a)
+        x00 = lerp(acc[0], acc[1], u)
+        x10 = lerp(acc[2], acc[3], u)
+        x01 = lerp(acc[4], acc[5], u)
+        x11 = lerp(acc[6], acc[7], u)
+        out[k] = lerp(lerp(x00, x10, v), lerp(x01, x11, v), w)
+    return out
+
+
+def perlin_phantom(g: Geometry, feature_um: float = 3.0, octaves: int = 3,
+                   sigma: float = 0.03, gen: np.random.Generator | None = None):
+    """Synthetic scattering tissue of Perlin noise: n = n0 + sigma * P, P a sum
+    of `octaves` noise octaves (lattice spacing feature_um, halved per octave,
+    amplitude halved) shifted to zero mean and scaled to unit standard
+    deviation (the adaptive-optics paragraph's tissue n = 1.36 +- 0.03, the
+    spread read as a standard deviation, with g.n0 = 1.36).  Returns dn = n - n0
+    as float32 [steps][ny][nx]."""
+    gen = rng(5, 0) if gen is None else gen
+    shape = (g.steps, g.ny, g.nx)
+    p = np.zeros(shape)
+    for o in range(octaves):
+        p += perlin_noise(shape, max(feature_um / g.dx / 2 ** o, 1.0), gen) / 2 ** o
+    p -= p.mean()
+    p /= p.std()
+    return (sigma * p).astype(np.float32)
+
+
+def ao_workload(nxy: int = 256, steps: int = 80):
+    """Adaptive-optics workload: a Perlin-noise tissue (n = 1.36 +- 0.03,
+    features ~3 um) of nxy^2 x steps voxels at dx = dz = 0.2 um, lambda =
+    0.5 um, background n0 = 1.36 (80 slices = 16 um, about four scattering mean
+    free paths); a Gaussian-apodised NA 0.6 pupil focusing at the exit plane
+    (z_f = steps dz).  Returns (geometry, dn, pupil amplitude, z_f)."""
+    g = Geometry(nxy, nxy, steps, 0.2, 0.2, 0.5, 1.36)
+    dn = perlin_phantom(g, gen=rng(5, 0))
+    k0 = 2 * np.pi / g.wavelength
+    kx, ky = _spatial_freqs(g.nx, g.ny, g.dx)
+    kt2 = kx ** 2 + ky ** 2
+    kmax = k0 * 0.6
+    amp = np.where(kt2 <= kmax ** 2, np.exp(-kt2 / kmax ** 2), 0.0).astype(np.float32)
+    return g, dn, amp, g.steps * g.dz
+
+
+# ---------------------------------------------------------------------------
 # workloads
 
 def config0():

@@ -112,9 +112,13 @@ def test_adjoint_validation(L):
     rc = L.bpm_adjoint(b.p, b.p, 64, 64, 4, 0.2, 0.2, 0.5, 1.33, None, None, b.p, None, None,
                        5, b.p, ws, None)
     assert rc == B.BPM_ERR_INVALID_ARG and b"checkpoint_every" in L.bpm_last_error()
-    rc = L.bpm_adjoint(None, b.p, 64, 64, 4, 0.2, 0.2, 0.5, 1.33, None, None, b.p, None, None,
+    # field_in may be NULL only for the linear adjoint (no intensity or dn gradient)
+    rc = L.bpm_adjoint(None, b.p, 64, 64, 4, 0.2, 0.2, 0.5, 1.33, None, None, b.p, None, b.p,
                        0, b.p, ws, None)
-    assert rc == B.BPM_ERR_INVALID_ARG
+    assert rc == B.BPM_ERR_INVALID_ARG and b"field_in" in L.bpm_last_error()
+    rc = L.bpm_adjoint(None, b.p, 64, 64, 4, 0.2, 0.2, 0.5, 1.33, b.p, b.p, b.p, None, None,
+                       0, b.p, ws, None)
+    assert rc == B.BPM_ERR_INVALID_ARG and b"field_in" in L.bpm_last_error()
     rc = L.bpm_adjoint(b.p, b.p, 64, 64, 4, 0.2, 0.2, 0.5, 1.33, None, None, b.p, None, None,
                        0, b.p, 100, None)
     assert rc == B.BPM_ERR_WORKSPACE
@@ -153,6 +157,17 @@ def test_helper_validation(L):
     assert L.bpm_pupil_spectrum(b.p, b.p, 64, 64, 0.2, 0.5, 1.33, float("nan"), b.p, None) == \
         B.BPM_ERR_NOT_FINITE
     assert L.bpm_pupil_phase_grad(None, b.p, 64, 64, b.p, None) == B.BPM_ERR_INVALID_ARG
+    assert L.bpm_guide_star_phase(b.p, 64, 64, 0.2, 0.5, 1.36, 3.0, float("inf"), 0.0, b.p,
+                                  None) == B.BPM_ERR_NOT_FINITE
+    assert L.bpm_guide_star_phase(None, 64, 64, 0.2, 0.5, 1.36, 3.0, 0.0, 0.0, b.p,
+                                  None) == B.BPM_ERR_INVALID_ARG
+    assert L.bpm_guide_star_phase(b.p, 64, 96, 0.2, 0.5, 1.36, 3.0, 0.0, 0.0, b.p,
+                                  None) == B.BPM_ERR_UNSUPPORTED_SIZE
+    assert L.bpm_adam_step(b.p, b.p, b.p, b.p, 16, 0.1, 0, None) == B.BPM_ERR_INVALID_ARG
+    assert L.bpm_adam_step(b.p, b.p, b.p, b.p, -1, 0.1, 1, None) == B.BPM_ERR_INVALID_ARG
+    assert L.bpm_adam_step(b.p, b.p, b.p, b.p, 16, float("nan"), 1, None) == B.BPM_ERR_NOT_FINITE
+    assert L.bpm_adam_step(b.p, None, b.p, b.p, 16, 0.1, 1, None) == B.BPM_ERR_INVALID_ARG
+    assert L.bpm_adam_step(None, None, None, None, 0, 0.1, 1, None) == B.BPM_OK
 
 
 def test_surrogate_validation(L):
