@@ -293,6 +293,51 @@ int bpm_psf_readout(const bpm_c64* exit_field, int nx, int ny, double dx, double
                     int n_src, int planes, int crop, double scale, float* psf_out,
                     void* workspace, size_t workspace_bytes, void* hip_stream);
 
+/* Bytes of workspace for bpm_pupil_fields. */
+size_t bpm_pupil_fields_workspace_size(int nx, int ny);
+
+/* Pupil fields of the sources of a multiplexed run (main-text paragraph on
+ * the light-sheet simulation: sample-induced aberrations extracted as
+ * spatially resolved Zernike maps).  With the detection pupil P and the
+ * refocusing of bpm_psf_readout, the complex source plane is
+ *     E0 = IDFT2( DFT2(exit) . P . exp(-i kz back_steps dz) )
+ * and source s = (sy, sx) gets the 2-D DFT of its crop x crop window, the
+ * source at window index (crop/2, crop/2):
+ *     pupil[s][l][m] = sum_{y,x < crop} E0(sy - crop/2 + y, sx - crop/2 + x)
+ *                      exp(-2 pi i (l y + m x) / crop)      (periodic indices).
+ * sources: device int32 [n_src][2]; pupil_out: device complex64
+ * [n_src][crop][crop], natural DFT order; crop 16, 32 or 64 (at most
+ * min(nx, ny)).  Workspace: bpm_pupil_fields_workspace_size bytes. */
+int bpm_pupil_fields(const bpm_c64* exit_field, int nx, int ny, double dx, double dz,
+                     double wavelength, double n0, double na, int back_steps, const int* sources,
+                     int n_src, int crop, bpm_c64* pupil_out, void* workspace,
+                     size_t workspace_bytes, void* hip_stream);
+
+/* Bytes of workspace for bpm_zernike_fit (0 for unsupported arguments). */
+size_t bpm_zernike_workspace_size(int crop, int n_modes);
+
+/* Zernike coefficients of the pupil fields of bpm_pupil_fields.  On the disc
+ * D = {l'^2 + m'^2 <= R^2}, R = NA crop dx / wavelength (signed frequency
+ * indices l', m'; R < crop/2 - 1 and at least 2 n_modes samples, else
+ * BPM_ERR_INVALID_ARG), rho = sqrt(l'^2 + m'^2) / R, theta = atan2(l', m'):
+ *   Y = pupil (-1)^(l + m); t_x = arg sum Y(l, m+1) conj Y(l, m) over pairs
+ *   in D, t_y likewise along l; p0 = arg sum_D Y exp(-i (t_x m' + t_y l'));
+ *   T = t_x m' + t_y l' + p0; W = wrap(arg Y - T) + T  (wrap to [-pi, pi));
+ *   c = P W, then twice c += P wrap(W - Z c), with Z[i][j] = Z_{j+1}(rho_i,
+ *   theta_i) the Noll-normalised Zernike polynomials (Noll 1976; unit mean
+ *   square on the unit disc) and P = (Z^T Z)^-1 Z^T over D;
+ *   rms = sqrt(mean_D wrap(W - Z c)^2).
+ * The coefficients are radians of pupil phase: c_1 piston, c_2 / c_3 tilt
+ * (a lateral source shift s gives c_2 = -k0 NA s_x / 2), c_4 defocus, ...
+ * coeffs_out: device float32 [n_src][n_modes] (n_modes 1..28); rms_out:
+ * [n_src] or NULL.  The fit assumes the phase after tilt removal varies by
+ * less than pi between neighbouring samples; rms reports what it leaves.
+ * Workspace: bpm_zernike_workspace_size bytes.  The call waits for the basis
+ * set-up on its stream. */
+int bpm_zernike_fit(const bpm_c64* pupil, int n_src, int crop, double dx, double wavelength,
+                    double na, int n_modes, float* coeffs_out, float* rms_out, void* workspace,
+                    size_t workspace_bytes, void* hip_stream);
+
 /* Bytes of workspace for bpm_point_sources. */
 size_t bpm_point_sources_workspace_size(int nx, int ny);
 

@@ -42,6 +42,8 @@ EXPORTS = (
     "bpm_march_variant", "bpm_march_variant_eligible", "bpm_set_march_variant",
     "bpm_propagate_adapted", "bpm_slice_means",
     "bpm_guide_star_phase", "bpm_adam_step",
+    "bpm_pupil_fields_workspace_size", "bpm_pupil_fields", "bpm_zernike_workspace_size",
+    "bpm_zernike_fit",
 )
 BPM_MARCH_AUTO = 0
 BPM_MARCH_ONE_PER_CU = 1
@@ -128,6 +130,14 @@ def _declare(L):
     L.bpm_guide_star_phase.restype = _I
     L.bpm_adam_step.argtypes = [_V, _V, _V, _V, ctypes.c_long, ctypes.c_float, _I, _V]
     L.bpm_adam_step.restype = _I
+    L.bpm_pupil_fields_workspace_size.argtypes = [_I, _I]
+    L.bpm_pupil_fields_workspace_size.restype = _Z
+    L.bpm_pupil_fields.argtypes = [_V, _I, _I, _D, _D, _D, _D, _D, _I, _V, _I, _I, _V, _V, _Z, _V]
+    L.bpm_pupil_fields.restype = _I
+    L.bpm_zernike_workspace_size.argtypes = [_I, _I]
+    L.bpm_zernike_workspace_size.restype = _Z
+    L.bpm_zernike_fit.argtypes = [_V, _I, _I, _D, _D, _D, _I, _V, _V, _V, _Z, _V]
+    L.bpm_zernike_fit.restype = _I
     L.bpm_psf_readout_workspace_size.argtypes = [_I, _I, _I]
     L.bpm_psf_readout_workspace_size.restype = _Z
     L.bpm_psf_readout.argtypes = [_V, _I, _I, _D, _D, _D, _D, _D, _I, _V, _I, _I, _I, _D, _V,

@@ -711,6 +711,93 @@ int bpm_psf_readout(const bpm_c64* exit_field, int nx, int ny, double dx, double
                          "psf readout");
 }
 
+size_t bpm_pupil_fields_workspace_size(int nx, int ny) {
+    if (!pow2_in_range(nx) || !pow2_in_range(ny)) return 0;
+    return bpm::pupil_fields_bytes(nx, ny);
+}
+
+static bool zernike_crop(int crop) { return crop == 16 || crop == 32 || crop == 64; }
+
+int bpm_pupil_fields(const bpm_c64* exit_field, int nx, int ny, double dx, double dz,
+                     double wavelength, double n0, double na, int back_steps, const int* sources,
+                     int n_src, int crop, bpm_c64* pupil_out, void* workspace,
+                     size_t workspace_bytes, void* hip_stream) {
+    int rc = check_geom(nx, ny, 0, dx, dz, wavelength, n0);
+    if (rc) return rc;
+    if (!std::isfinite(na) || !(na > 0)) return fail(BPM_ERR_NOT_FINITE, "na=%g must be > 0", na);
+    if (!zernike_crop(crop) || crop > nx || crop > ny)
+        return fail(BPM_ERR_INVALID_ARG, "crop=%d must be 16, 32 or 64 and at most min(nx, ny)",
+                    crop);
+    if (back_steps < 0 || n_src < 0)
+        return fail(BPM_ERR_INVALID_ARG, "back_steps=%d and n_src=%d must be >= 0", back_steps,
+                    n_src);
+    if (!exit_field || (n_src > 0 && (!sources || !pupil_out)))
+        return fail(BPM_ERR_INVALID_ARG, "exit_field, sources and pupil_out must be non-null");
+    if (!aligned(exit_field, 8) || (sources && !aligned(sources, 4)) ||
+        (pupil_out && !aligned(pupil_out, 8)))
+        return fail(BPM_ERR_INVALID_ARG, "misaligned array");
+    if ((rc = check_workspace(workspace, workspace_bytes, bpm::pupil_fields_bytes(nx, ny))))
+        return rc;
+    const bpm::PupilFieldArgs r{exit_field, nx, ny, dx, dz, wavelength, n0, na, back_steps,
+                                sources, n_src, crop, pupil_out};
+    return device_status(bpm::launch_pupil_fields(r, workspace,
+                                                  static_cast<hipStream_t>(hip_stream)),
+                         "pupil fields");
+}
+
+// points (l', m') of the crop's signed DFT grid with l'^2 + m'^2 <= R^2
+static int disc_points(int crop, double R) {
+    int n = 0;
+    for (int l = -crop / 2; l < crop / 2; ++l)
+        for (int m = -crop / 2; m < crop / 2; ++m)
+            if ((double)(l * l + m * m) <= R * R) ++n;
+    return n;
+}
+
+size_t bpm_zernike_workspace_size(int crop, int n_modes) {
+    if (!zernike_crop(crop) || n_modes < 1 || n_modes > bpm::kMaxZernike) return 0;
+    return bpm::zernike_bytes(crop, n_modes);
+}
+
+int bpm_zernike_fit(const bpm_c64* pupil, int n_src, int crop, double dx, double wavelength,
+                    double na, int n_modes, float* coeffs_out, float* rms_out, void* workspace,
+                    size_t workspace_bytes, void* hip_stream) {
+    if (!std::isfinite(dx) || !std::isfinite(wavelength) || !std::isfinite(na) || !(dx > 0) ||
+        !(wavelength > 0) || !(na > 0))
+        return fail(BPM_ERR_NOT_FINITE, "dx=%g, wavelength=%g and na=%g must be finite and > 0",
+                    dx, wavelength, na);
+    if (!zernike_crop(crop) || n_modes < 1 || n_modes > bpm::kMaxZernike || n_src < 0)
+        return fail(BPM_ERR_INVALID_ARG,
+                    "crop=%d must be 16, 32 or 64, n_modes=%d in 1..%d, n_src=%d >= 0", crop,
+                    n_modes, bpm::kMaxZernike, n_src);
+    const double R = na * crop * dx / wavelength;
+    if (!(R < crop / 2 - 1))
+        return fail(BPM_ERR_INVALID_ARG,
+                    "the pupil disc (radius NA crop dx / wavelength = %g samples) must lie "
+                    "inside the window's band (radius < %d)", R, crop / 2 - 1);
+    const int disc_n = disc_points(crop, R);
+    if (disc_n < 2 * n_modes)
+        return fail(BPM_ERR_INVALID_ARG,
+                    "the pupil disc holds %d samples, fewer than 2 n_modes = %d", disc_n,
+                    2 * n_modes);
+    if (n_src > 0 && (!pupil || !coeffs_out))
+        return fail(BPM_ERR_INVALID_ARG, "pupil and coeffs_out must be non-null");
+    if ((pupil && !aligned(pupil, 8)) || (coeffs_out && !aligned(coeffs_out, 4)) ||
+        (rms_out && !aligned(rms_out, 4)))
+        return fail(BPM_ERR_INVALID_ARG, "misaligned array");
+    int rc = check_workspace(workspace, workspace_bytes, bpm::zernike_bytes(crop, n_modes));
+    if (rc) return rc;
+    const bpm::ZernikeArgs a{pupil, n_src, crop, n_modes, disc_n, dx, wavelength, na, coeffs_out,
+                             rms_out};
+    int ok = 0;
+    rc = device_status(bpm::launch_zernike_fit(a, workspace, &ok,
+                                               static_cast<hipStream_t>(hip_stream)),
+                       "zernike fit");
+    if (rc) return rc;
+    if (!ok) return fail(BPM_ERR_INVALID_ARG, "the Zernike normal matrix is not positive definite");
+    return BPM_OK;
+}
+
 size_t bpm_point_sources_workspace_size(int nx, int ny) {
     if (!pow2_in_range(nx) || !pow2_in_range(ny)) return 0;
     return bpm::sources_bytes(nx, ny);

@@ -149,6 +149,29 @@ struct ReadoutArgs {
 size_t readout_bytes(int nx, int ny, int planes);
 hipError_t launch_readout(const ReadoutArgs& r, void* ws, hipStream_t s);
 
+// Pupil fields and Zernike fits of sample-induced aberrations (readout.hip).
+constexpr int kMaxZernike = 28;
+struct PupilFieldArgs {
+    const void* exit_field;
+    int nx, ny;
+    double dx, dz, wavelength, n0, na;
+    int back_steps;
+    const int* sources;  // device [n_src][2] (y, x)
+    int n_src, crop;
+    void* pupil_out;  // float2 [n_src][crop][crop]
+};
+size_t pupil_fields_bytes(int nx, int ny);
+hipError_t launch_pupil_fields(const PupilFieldArgs& r, void* ws, hipStream_t s);
+struct ZernikeArgs {
+    const void* pupil;  // float2 [n_src][crop][crop]
+    int n_src, crop, n_modes, disc_n;
+    double dx, wavelength, na;
+    float* coeffs_out;  // [n_src][n_modes]
+    float* rms_out;     // [n_src] or nullptr
+};
+size_t zernike_bytes(int crop, int n_modes);
+hipError_t launch_zernike_fit(const ZernikeArgs& a, void* ws, int* host_ok, hipStream_t s);
+
 // Multiplexed point-source input field (sources.hip).
 struct SourceArgs {
     const int* positions;  // device [n_src][2] (y, x)

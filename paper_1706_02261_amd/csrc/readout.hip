@@ -155,4 +155,449 @@ hipError_t launch_readout(const ReadoutArgs& r, void* ws, hipStream_t s) {
     return hipGetLastError();
 }
 
+// ---------------------------------------------------------------------------
+// Pupil fields and Zernike fits of the sample-induced aberrations.
+//
+//   E0     = IDFT2( DFT2(u) . P . exp(-i kz back dz) )       (complex, 1 / (nx ny))
+//   X_s    = DFT2 of the crop x crop window of E0 whose centre (index crop/2)
+//            is source s
+//   fit    : on the disc D of the window's DFT grid, Y = X (-1)^(l+m); tilt
+//            t_x = arg sum Y(l, m+1) conj Y(l, m), t_y likewise, piston p0;
+//            T = t_x m' + t_y l' + p0, W = wrap(arg Y - T) + T; c = P W then
+//            twice c += P wrap(W - Z c); rms = sqrt(mean_D wrap(W - Z c)^2),
+//            Z the Noll-normalised Zernike polynomials on D, P = (Z^T Z)^-1 Z^T.
+
+// complex row IDFT of the column pass output: E = scale * IDFT_rows(T)
+template <int NX>
+__global__ __launch_bounds__(kBlock) void refocus_rows_kernel(const float2* __restrict__ T,
+                                                              float2* __restrict__ E, int ny,
+                                                              float scale,
+                                                              const float2* __restrict__ tw,
+                                                              const int* __restrict__ permx) {
+    constexpr int T_ = NX / kR, B = units_per_block<NX>();
+    extern __shared__ float2 smem[];
+    const int sub = threadIdx.x / T_, tau = threadIdx.x % T_;
+    const int row = blockIdx.x * B + sub;
+    const bool on = row < ny;
+    const size_t rowoff = (size_t)(on ? row : 0) * NX;
+    Twiddles<NX, kR> twx;
+    twx.load(tw, tau);
+    float2 v[kR];
+#pragma unroll
+    for (int i = 0; i < kR; ++i) v[i] = c_conj(T[rowoff + i * T_ + tau]);
+    fft_forward<NX, kR, 1>(v, smem + sub * lds_size<NX>(), tau, twx, BlockSync());
+    if (on) {
+#pragma unroll
+        for (int r = 0; r < kR; ++r)
+            E[rowoff + permx[r * T_ + tau]] = make_float2(scale * v[r].x, -scale * v[r].y);
+    }
+}
+
+constexpr int kAbBlock = 256;
+
+// z + a b
+__device__ __forceinline__ float2 c_fma(float2 a, float2 b, float2 z) {
+    return make_float2(fmaf(a.x, b.x, fmaf(-a.y, b.y, z.x)), fmaf(a.x, b.y, fmaf(a.y, b.x, z.y)));
+}
+
+// X_s: gather the C x C window of E around source s, then its 2-D DFT
+// (row and column DFTs as direct sums over an LDS-resident window).
+template <int C>
+__global__ __launch_bounds__(kAbBlock) void pupil_crop_kernel(const float2* __restrict__ E,
+                                                              const int* __restrict__ src,
+                                                              int nx, int ny,
+                                                              float2* __restrict__ out) {
+    constexpr int CC = C * C, PER = (CC + kAbBlock - 1) / kAbBlock, LD = C + 1;
+    __shared__ float2 a[C * LD];
+    __shared__ float2 tw[C];
+    const int s = blockIdx.x;
+    const int sy = src[2 * s], sx = src[2 * s + 1];
+    for (int i = threadIdx.x; i < C; i += kAbBlock) {
+        double sv, cv;
+        sincospi(-2.0 * i / C, &sv, &cv);
+        tw[i] = make_float2((float)cv, (float)sv);
+    }
+    for (int e = threadIdx.x; e < CC; e += kAbBlock) {
+        const int y = e / C, x = e % C;
+        const int gy = ((sy - C / 2 + y) % ny + ny) % ny;
+        const int gx = ((sx - C / 2 + x) % nx + nx) % nx;
+        a[y * LD + x] = E[(size_t)gy * nx + gx];
+    }
+    __syncthreads();
+    float2 acc[PER];
+#pragma unroll
+    for (int q = 0; q < PER; ++q) {
+        const int e = threadIdx.x + q * kAbBlock;
+        float2 z = make_float2(0.f, 0.f);
+        if (e < CC) {
+            const int y = e / C, m = e % C;
+            for (int x = 0; x < C; ++x) z = c_fma(a[y * LD + x], tw[(m * x) & (C - 1)], z);
+        }
+        acc[q] = z;
+    }
+    __syncthreads();
+#pragma unroll
+    for (int q = 0; q < PER; ++q) {
+        const int e = threadIdx.x + q * kAbBlock;
+        if (e < CC) a[(e / C) * LD + e % C] = acc[q];
+    }
+    __syncthreads();
+#pragma unroll
+    for (int q = 0; q < PER; ++q) {
+        const int e = threadIdx.x + q * kAbBlock;
+        if (e < CC) {
+            const int l = e / C, m = e % C;
+            float2 z = make_float2(0.f, 0.f);
+            for (int y = 0; y < C; ++y) z = c_fma(a[y * LD + m], tw[(l * y) & (C - 1)], z);
+            out[(size_t)s * CC + e] = z;
+        }
+    }
+}
+
+// Noll index j >= 1 -> (n, m), m < 0 for the sine terms (odd j)
+__device__ inline void noll_nm(int j, int& n, int& m) {
+    int nn = 0;
+    while ((nn + 1) * (nn + 2) / 2 < j) ++nn;
+    const int k = j - nn * (nn + 1) / 2 - 1;
+    int mm = nn % 2 + 2 * ((k + 1 - nn % 2) / 2);
+    if (mm != 0 && (j & 1)) mm = -mm;
+    n = nn;
+    m = mm;
+}
+
+__device__ inline double factorial_d(int n) {
+    double f = 1.0;
+    for (int i = 2; i <= n; ++i) f *= i;
+    return f;
+}
+
+// Noll-normalised Zernike polynomial Z_j(rho, theta)
+__device__ double zernike_d(int j, double rho, double theta) {
+    int n, m;
+    noll_nm(j, n, m);
+    const int am = m < 0 ? -m : m;
+    double r = 0.0;
+    for (int s = 0; s <= (n - am) / 2; ++s) {
+        const double c = ((s & 1) ? -1.0 : 1.0) * factorial_d(n - s) /
+                         (factorial_d(s) * factorial_d((n + am) / 2 - s) *
+                          factorial_d((n - am) / 2 - s));
+        r += c * pow(rho, (double)(n - 2 * s));
+    }
+    if (m == 0) return sqrt((double)(n + 1)) * r;
+    return sqrt(2.0 * (n + 1)) * r * (m > 0 ? cos(am * theta) : sin(am * theta));
+}
+
+// One workgroup: the basis Z [J][C*C] on the disc (zero outside) and the
+// least-squares operator P = (Z^T Z)^-1 Z^T [J][C*C], both float; Zd is a
+// double scratch [J][C*C].  R2 = (NA C dx / lambda)^2, R its root.
+template <int C>
+__global__ __launch_bounds__(kAbBlock) void zernike_basis_kernel(int J, double R,
+                                                                 double* __restrict__ Zd,
+                                                                 float* __restrict__ Zf,
+                                                                 float* __restrict__ Pf,
+                                                                 int* __restrict__ ok) {
+    constexpr int CC = C * C;
+    __shared__ double G[kMaxZernike * kMaxZernike];
+    __shared__ double Gi[kMaxZernike * kMaxZernike];
+    for (int i = threadIdx.x; i < CC; i += kAbBlock) {
+        const int l = i / C, m = i % C;
+        const int ls = l < C / 2 ? l : l - C, ms = m < C / 2 ? m : m - C;
+        const bool in = (double)(ls * ls + ms * ms) <= R * R;
+        const double rho = sqrt((double)(ls * ls + ms * ms)) / R;
+        const double th = atan2((double)ls, (double)ms);
+        for (int j = 0; j < J; ++j) Zd[(size_t)j * CC + i] = in ? zernike_d(j + 1, rho, th) : 0.0;
+    }
+    __syncthreads();
+    for (int p = threadIdx.x; p < J * J; p += kAbBlock) {
+        const int a = p / J, b = p % J;
+        double acc = 0.0;
+        if (b <= a)
+            for (int i = 0; i < CC; ++i) acc += Zd[(size_t)a * CC + i] * Zd[(size_t)b * CC + i];
+        G[p] = acc;
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        // Cholesky G = L L^T in the lower triangle, then Gi = G^-1 column by column
+        int good = 1;
+        for (int c = 0; c < J && good; ++c) {
+            double d = G[c * J + c];
+            for (int k = 0; k < c; ++k) d -= G[c * J + k] * G[c * J + k];
+            if (!(d > 0.0)) {
+                good = 0;
+                break;
+            }
+            d = sqrt(d);
+            G[c * J + c] = d;
+            for (int r = c + 1; r < J; ++r) {
+                double v = G[r * J + c];
+                for (int k = 0; k < c; ++k) v -= G[r * J + k] * G[c * J + k];
+                G[r * J + c] = v / d;
+            }
+        }
+        for (int col = 0; col < J && good; ++col) {
+            double y[kMaxZernike];
+            for (int r = 0; r < J; ++r) {
+                double v = (r == col) ? 1.0 : 0.0;
+                for (int k = 0; k < r; ++k) v -= G[r * J + k] * y[k];
+                y[r] = v / G[r * J + r];
+            }
+            for (int r = J - 1; r >= 0; --r) {
+                double v = y[r];
+                for (int k = r + 1; k < J; ++k) v -= G[k * J + r] * Gi[k * J + col];
+                Gi[r * J + col] = v / G[r * J + r];
+            }
+        }
+        *ok = good;
+    }
+    __syncthreads();
+    for (int i = threadIdx.x; i < CC; i += kAbBlock) {
+        for (int j = 0; j < J; ++j) {
+            double acc = 0.0;
+            for (int k = 0; k < J; ++k) acc += Gi[j * J + k] * Zd[(size_t)k * CC + i];
+            Pf[(size_t)j * CC + i] = (float)acc;
+            Zf[(size_t)j * CC + i] = (float)Zd[(size_t)j * CC + i];
+        }
+    }
+}
+
+// sum of K values over the workgroup; every thread gets the totals in out
+template <int K>
+__device__ inline void block_sum(float (&v)[K], float* red, float* out) {
+    const int lane = threadIdx.x % 64, wave = threadIdx.x / 64;
+#pragma unroll
+    for (int k = 0; k < K; ++k) {
+        float x = v[k];
+        for (int o = 32; o > 0; o >>= 1) x += __shfl_xor(x, o);
+        if (lane == 0) red[wave * K + k] = x;
+    }
+    __syncthreads();
+    if (threadIdx.x < K) {
+        float t = 0.f;
+        for (int w = 0; w < kAbBlock / 64; ++w) t += red[w * K + threadIdx.x];
+        out[threadIdx.x] = t;
+    }
+    __syncthreads();
+}
+
+__device__ inline float wrap_pi(float p) {
+    const float kPi = 3.14159265358979f;
+    return p - 2.f * kPi * floorf((p + kPi) / (2.f * kPi));
+}
+
+// one workgroup per source
+template <int C>
+__global__ __launch_bounds__(kAbBlock) void zernike_fit_kernel(const float2* __restrict__ X,
+                                                               int J, double R, int disc_n,
+                                                               const float* __restrict__ Zf,
+                                                               const float* __restrict__ Pf,
+                                                               float* __restrict__ coeffs,
+                                                               float* __restrict__ rms) {
+    constexpr int CC = C * C, PER = (CC + kAbBlock - 1) / kAbBlock;
+    __shared__ float red[(kAbBlock / 64) * kMaxZernike];
+    __shared__ float tot[kMaxZernike];
+    const int s = blockIdx.x;
+    const float2* Xs = X + (size_t)s * CC;
+    auto inside = [&](int l, int m) {
+        const int ls = l < C / 2 ? l : l - C, ms = m < C / 2 ? m : m - C;
+        return (double)(ls * ls + ms * ms) <= R * R;
+    };
+    auto Yat = [&](int l, int m) {
+        const float2 x = Xs[l * C + m];
+        return ((l + m) & 1) ? make_float2(-x.x, -x.y) : x;
+    };
+    float W[PER];
+    bool in[PER];
+    // tilt
+    float t4[4] = {0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+    for (int q = 0; q < PER; ++q) {
+        const int e = threadIdx.x + q * kAbBlock;
+        in[q] = false;
+        if (e < CC) {
+            const int l = e / C, m = e % C;
+            in[q] = inside(l, m);
+            if (in[q]) {
+                const float2 y = Yat(l, m);
+                const int m1 = (m + 1) & (C - 1), l1 = (l + 1) & (C - 1);
+                if (inside(l, m1)) {
+                    const float2 z = c_mul(Yat(l, m1), c_conj(y));
+                    t4[0] += z.x;
+                    t4[1] += z.y;
+                }
+                if (inside(l1, m)) {
+                    const float2 z = c_mul(Yat(l1, m), c_conj(y));
+                    t4[2] += z.x;
+                    t4[3] += z.y;
+                }
+            }
+        }
+    }
+    block_sum<4>(t4, red, tot);
+    const float tx = atan2f(tot[1], tot[0]), ty = atan2f(tot[3], tot[2]);
+    // piston
+    float p2[2] = {0.f, 0.f};
+#pragma unroll
+    for (int q = 0; q < PER; ++q) {
+        const int e = threadIdx.x + q * kAbBlock;
+        if (in[q]) {
+            const int l = e / C, m = e % C;
+            const int ls = l < C / 2 ? l : l - C, ms = m < C / 2 ? m : m - C;
+            float sv, cv;
+            sincosf(-(tx * ms + ty * ls), &sv, &cv);
+            const float2 z = c_mul(Yat(l, m), make_float2(cv, sv));
+            p2[0] += z.x;
+            p2[1] += z.y;
+        }
+    }
+    block_sum<2>(p2, red, tot);
+    const float p0 = atan2f(tot[1], tot[0]);
+#pragma unroll
+    for (int q = 0; q < PER; ++q) {
+        const int e = threadIdx.x + q * kAbBlock;
+        W[q] = 0.f;
+        if (in[q]) {
+            const int l = e / C, m = e % C;
+            const int ls = l < C / 2 ? l : l - C, ms = m < C / 2 ? m : m - C;
+            const float T = tx * ms + ty * ls + p0;
+            const float2 y = Yat(l, m);
+            W[q] = wrap_pi(atan2f(y.y, y.x) - T) + T;
+        }
+    }
+    // c = P W, then two passes c += P wrap(W - Z c)
+    float c[kMaxZernike];
+    for (int j = 0; j < kMaxZernike; ++j) c[j] = 0.f;
+    for (int pass = 0; pass < 3; ++pass) {
+        float part[kMaxZernike];
+        for (int j = 0; j < kMaxZernike; ++j) part[j] = 0.f;
+#pragma unroll
+        for (int q = 0; q < PER; ++q) {
+            const int e = threadIdx.x + q * kAbBlock;
+            if (in[q]) {
+                float r = W[q];
+                if (pass > 0) {
+                    float zc = 0.f;
+                    for (int j = 0; j < J; ++j) zc += Zf[(size_t)j * CC + e] * c[j];
+                    r = wrap_pi(W[q] - zc);
+                }
+                for (int j = 0; j < J; ++j) part[j] += Pf[(size_t)j * CC + e] * r;
+            }
+        }
+        block_sum<kMaxZernike>(part, red, tot);
+        for (int j = 0; j < J; ++j) c[j] += tot[j];
+    }
+    float e2[1] = {0.f};
+#pragma unroll
+    for (int q = 0; q < PER; ++q) {
+        const int e = threadIdx.x + q * kAbBlock;
+        if (in[q]) {
+            float zc = 0.f;
+            for (int j = 0; j < J; ++j) zc += Zf[(size_t)j * CC + e] * c[j];
+            const float r = wrap_pi(W[q] - zc);
+            e2[0] += r * r;
+        }
+    }
+    block_sum<1>(e2, red, tot);
+    if (threadIdx.x < J) coeffs[(size_t)s * J + threadIdx.x] = c[threadIdx.x];
+    if (threadIdx.x == 0 && rms) rms[s] = sqrtf(tot[0] / (float)disc_n);
+}
+
+size_t pupil_fields_bytes(int nx, int ny) {
+    const size_t n = (size_t)nx * ny;
+    return plan_bytes(nx, ny) + 2 * align_up(sizeof(float2) * n);
+}
+
+hipError_t launch_pupil_fields(const PupilFieldArgs& r, void* ws, hipStream_t s) {
+    const size_t n = (size_t)r.nx * r.ny;
+    char* b = static_cast<char*>(ws);
+    const Plan p = plan_carve(b, r.nx, r.ny);
+    b += plan_bytes(r.nx, r.ny);
+    float2* S = (float2*)b;
+    b += align_up(sizeof(float2) * n);
+    float2* T = (float2*)b;
+    const Geom g{r.nx, r.ny, 0, r.dx, r.dz, r.wavelength, r.n0};
+    hipError_t e = launch_plan(g, p, false, s);
+    if (e == hipSuccess) e = launch_fft2(r.exit_field, S, r.nx, r.ny, false, 1.0f, p, s);
+    if (e != hipSuccess) return e;
+    const double kPi = 3.14159265358979323846;
+    const double k = 2.0 * kPi * r.n0 / r.wavelength;
+    double pthr = (double)r.nx * (double)r.ny * r.na * r.dx / r.wavelength;
+    pthr *= pthr;
+    const float scale = (float)(1.0 / ((double)r.nx * r.ny));
+    auto cols = [&](auto yc) -> hipError_t {
+        constexpr int NY = decltype(yc)::value, W = units_per_block<NY>();
+        readout_cols_kernel<NY><<<dim3((r.nx + W - 1) / W, 1), kBlock,
+                                  sizeof(float2) * W * lds_size<NY>(), s>>>(
+            S, T, r.nx, r.ny, r.dx, r.dz, k, pthr, r.back_steps, 1, (const float2*)p.twy,
+            (const int*)p.permy);
+        return hipGetLastError();
+    };
+    // E overwrites S (the spectrum is no longer needed after the column pass)
+    auto rows = [&](auto xc) -> hipError_t {
+        constexpr int NX = decltype(xc)::value, B = units_per_block<NX>();
+        refocus_rows_kernel<NX><<<(r.ny + B - 1) / B, kBlock, sizeof(float2) * B * lds_size<NX>(),
+                                  s>>>(T, S, r.ny, scale, (const float2*)p.twx,
+                                       (const int*)p.permx);
+        return hipGetLastError();
+    };
+    e = dispatch_size(r.ny, cols);
+    if (e == hipSuccess) e = dispatch_size(r.nx, rows);
+    if (e != hipSuccess || r.n_src == 0) return e;
+    switch (r.crop) {
+        case 16:
+            pupil_crop_kernel<16><<<r.n_src, kAbBlock, 0, s>>>(S, r.sources, r.nx, r.ny,
+                                                               (float2*)r.pupil_out);
+            break;
+        case 32:
+            pupil_crop_kernel<32><<<r.n_src, kAbBlock, 0, s>>>(S, r.sources, r.nx, r.ny,
+                                                               (float2*)r.pupil_out);
+            break;
+        case 64:
+            pupil_crop_kernel<64><<<r.n_src, kAbBlock, 0, s>>>(S, r.sources, r.nx, r.ny,
+                                                               (float2*)r.pupil_out);
+            break;
+        default:
+            return hipErrorInvalidValue;
+    }
+    return hipGetLastError();
+}
+
+size_t zernike_bytes(int crop, int n_modes) {
+    const size_t cc = (size_t)crop * crop * n_modes;
+    return align_up(sizeof(double) * cc) + 2 * align_up(sizeof(float) * cc) + 256;
+}
+
+hipError_t launch_zernike_fit(const ZernikeArgs& a, void* ws, int* host_ok, hipStream_t s) {
+    const size_t cc = (size_t)a.crop * a.crop * a.n_modes;
+    char* b = static_cast<char*>(ws);
+    double* Zd = (double*)b;
+    b += align_up(sizeof(double) * cc);
+    float* Zf = (float*)b;
+    b += align_up(sizeof(float) * cc);
+    float* Pf = (float*)b;
+    b += align_up(sizeof(float) * cc);
+    int* ok = (int*)b;
+    const double R = a.na * a.crop * a.dx / a.wavelength;
+    auto run = [&](auto cc_) -> hipError_t {
+        constexpr int C = decltype(cc_)::value;
+        zernike_basis_kernel<C><<<1, kAbBlock, 0, s>>>(a.n_modes, R, Zd, Zf, Pf, ok);
+        hipError_t e = hipGetLastError();
+        if (e != hipSuccess) return e;
+        if (a.n_src > 0)
+            zernike_fit_kernel<C><<<a.n_src, kAbBlock, 0, s>>>(
+                (const float2*)a.pupil, a.n_modes, R, a.disc_n, Zf, Pf, a.coeffs_out, a.rms_out);
+        e = hipGetLastError();
+        if (e == hipSuccess && host_ok) {
+            e = hipMemcpyAsync(host_ok, ok, sizeof(int), hipMemcpyDeviceToHost, s);
+            if (e == hipSuccess) e = hipStreamSynchronize(s);
+        }
+        return e;
+    };
+    switch (a.crop) {
+        case 16: return run(std::integral_constant<int, 16>{});
+        case 32: return run(std::integral_constant<int, 32>{});
+        case 64: return run(std::integral_constant<int, 64>{});
+        default: return hipErrorInvalidValue;
+    }
+}
+
 }  // namespace bpm

@@ -168,6 +168,21 @@ def test_helper_validation(L):
     assert L.bpm_adam_step(b.p, b.p, b.p, b.p, 16, float("nan"), 1, None) == B.BPM_ERR_NOT_FINITE
     assert L.bpm_adam_step(b.p, None, b.p, b.p, 16, 0.1, 1, None) == B.BPM_ERR_INVALID_ARG
     assert L.bpm_adam_step(None, None, None, None, 0, 0.1, 1, None) == B.BPM_OK
+    ws = L.bpm_pupil_fields_workspace_size(64, 64)
+    assert ws > 0 and L.bpm_pupil_fields_workspace_size(64, 48) == 0
+    assert L.bpm_pupil_fields(b.p, 64, 64, 0.2, 0.2, 0.5, 1.33, 0.6, 3, b.p, 2, 24, b.p, b.p, ws,
+                              None) == B.BPM_ERR_INVALID_ARG
+    assert L.bpm_pupil_fields(b.p, 64, 64, 0.2, 0.2, 0.5, 1.33, 0.6, 3, b.p, 2, 32, b.p, b.p,
+                              ws - 1, None) == B.BPM_ERR_WORKSPACE
+    assert L.bpm_zernike_workspace_size(32, 29) == 0 and L.bpm_zernike_workspace_size(32, 15) > 0
+    zws = L.bpm_zernike_workspace_size(32, 15)
+    # NA 0.05: the disc holds too few samples; NA 1.4 at dx 0.2: it leaves the window's band
+    assert L.bpm_zernike_fit(b.p, 2, 32, 0.2, 0.5, 0.05, 15, b.p, None, b.p, zws,
+                             None) == B.BPM_ERR_INVALID_ARG and b"samples" in L.bpm_last_error()
+    assert L.bpm_zernike_fit(b.p, 2, 32, 0.2, 0.5, 1.4, 15, b.p, None, b.p, zws,
+                             None) == B.BPM_ERR_INVALID_ARG and b"band" in L.bpm_last_error()
+    assert L.bpm_zernike_fit(b.p, 2, 32, 0.2, 0.5, 0.6, 15, b.p, None, b.p, zws - 1,
+                             None) == B.BPM_ERR_WORKSPACE
 
 
 def test_surrogate_validation(L):
