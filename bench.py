@@ -522,6 +522,60 @@ def ao_rates(dev, reps=5):
             "guide_star_ms_256x256x512": round(ms_gs3, 4)}
 
 
+def zernike_rates(dev, dn, g, depth=512, pitch=32, n_modes=15, reps=3):
+    """Aberration map of the detection volume: sources on a pitch-32 grid at
+    slice `depth` (1024 sources on 1024^2), one multiplexed march to the exit
+    plane, pupil fields (32 x 32 windows) and 15-mode Zernike fits; the
+    time of each part (median of `reps`) and sources per second."""
+    import numpy as np
+    import torch
+    from paper_1706_02261_amd import aberrations, psfs
+    from paper_1706_02261_amd import bpm as B
+    opt = psfs.Optics(g.dx, g.dz, g.wavelength, g.n0, 0.6)
+    nz, ny, nx = dn.shape
+    ys = torch.arange(pitch // 2, ny, pitch, dtype=torch.int32, device=dev)
+    xs = torch.arange(pitch // 2, nx, pitch, dtype=torch.int32, device=dev)
+    src = torch.stack(torch.meshgrid(ys, xs, indexing="ij"), -1).reshape(-1, 2).contiguous()
+    ws = B.workspace(B.workspace_size(nx, ny, nz - depth), dev)
+    state = {}
+
+    def march():
+        u0 = B.point_sources(src, nx, ny, opt.dx, opt.wavelength, opt.n0, opt.na, 0.0)
+        state["exit"], _ = B.propagate(u0, dn[depth:], opt.dx, opt.dz, opt.wavelength, opt.n0,
+                                       intensity=False, ws=ws)
+
+    def pupils():
+        state["X"] = aberrations.pupil_fields(state["exit"], src, nz - depth, opt, 32)
+
+    def fit():
+        state["c"] = aberrations.zernike_fit(state["X"], opt, n_modes)
+
+    out = {}
+    for name, fn in (("march_ms", march), ("pupil_fields_ms", pupils), ("zernike_fit_ms", fit)):
+        fn()
+        torch.cuda.synchronize(dev)
+        ts = []
+        for _ in range(reps):
+            a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            a.record()
+            fn()
+            b.record()
+            torch.cuda.synchronize(dev)
+            ts.append(a.elapsed_time(b))
+        out[name] = round(float(np.median(ts)), 3)
+    c, rms = state["c"]
+    total = out["march_ms"] + out["pupil_fields_ms"] + out["zernike_fit_ms"]
+    res = {"workload": f"{src.shape[0]} sources (pitch {pitch}) at slice {depth} of the "
+                       f"{nx}x{ny}x{nz} detection volume, {nz - depth}-slice multiplexed march, "
+                       f"32x32 pupil windows, {n_modes} Noll modes",
+           **out, "sources_per_s": round(src.shape[0] / (total / 1e3), 1),
+           "median_rms_rad": round(float(rms.median()), 4),
+           "max_abs_coeff_rad": round(float(c[:, 1:].abs().max()), 3)}
+    del state, ws
+    torch.cuda.empty_cache()
+    return res
+
+
 def phase_split(jobs, ws, stream, launch_ms):
     """One run of the timed launch with per-workgroup phase timers: mean and
     max over workgroups of each phase, in microseconds per step."""
@@ -691,11 +745,17 @@ def main():
     small = None
     if not (args.no_extra and args.no_cpu_baseline):
         small = {"128x128x64": synth.config0(), "512x512x512": synth.config1()}
+        g1, _, dn1 = small["512x512x512"]
+        # the same volume lit by a bound hexagonal Bessel lattice (NA 0.55 / 0.45)
+        small["512x512x512_bessel_lattice"] = (
+            g1, synth.bessel_lattice_field(g1.nx, g1.ny, g1.dx, g1.wavelength, g1.n0, 0.55,
+                                           0.45, 6, (0.08, 0.01)), dn1)
     if not args.no_extra:
         line["workloads"] = workload_rates(dev, small)
         line["adapted"] = adapted_rate(dev, jobs[0]["field"], jobs[0]["dn"], g)
         line["adjoint"] = adjoint_rate(dev)
         line["adaptive_optics"] = ao_rates(dev)
+        line["zernike_map"] = zernike_rates(dev, jobs[0]["dn"], g, depth=g.steps // 2)
         line["uneven_batch"] = batch_rate(dev)
     if not args.no_cpu_baseline:
         def gpu_first(steps):

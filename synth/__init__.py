@@ -1,7 +1,8 @@
 """Seeded synthetic inputs for the beam-propagation march.
 
 This module builds inputs only: refractive-index phantoms, source fields
-(single and multiplexed point sources, a cylindrical light sheet) and the
+(single and multiplexed point sources, a cylindrical light sheet, Bessel
+beams and Bessel lattices) and the
 job tables of uneven batches.  It holds none of the march's arithmetic (no
 propagator, no phase screen, no FFT of the march) and imports neither the
 CPU oracle nor the GPU package, so that both can be fed from it.
@@ -29,6 +30,8 @@ __all__ = [
     "rng", "lateral_coords", "axial_coords", "add_spheres", "sphere_phantom",
     "smoothed_noise", "point_source_spectrum", "point_source_field",
     "multiplexed_field", "jittered_grid", "light_sheet_field", "Geometry",
+    "bessel_spectrum", "bessel_field", "lattice_spectrum", "bessel_lattice_field",
+    "perlin_noise", "perlin_phantom", "ao_workload",
     "config0", "config1", "config2_detection", "config2_light_sheet",
     "config3", "batch_job_specs", "ellipsoid_phantom", "surrogate_volume",
 ]
@@ -293,6 +296,73 @@ def light_sheet_field(nx: int, ny: int, dx: float, wavelength: float, n0: float,
     u = np.roll(np.fft.ifft2(spec), shift, axis=(0, 1))
     u /= np.linalg.norm(u)
     return u.astype(np.complex64)
+
+
+# ---------------------------------------------------------------------------
+# Bessel beams and Bessel lattices (alternative light-sheet illuminations)
+
+def _annulus(nx, ny, dx, wavelength, na_outer, na_inner):
+    k0 = 2 * np.pi / wavelength
+    kx, ky = _spatial_freqs(nx, ny, dx)
+    kt2 = kx ** 2 + ky ** 2
+    if not 0 <= na_inner < na_outer:
+        raise ValueError("need 0 <= na_inner < na_outer")
+    return kx, ky, (kt2 >= (k0 * na_inner) ** 2) & (kt2 <= (k0 * na_outer) ** 2)
+
+
+def bessel_spectrum(nx: int, ny: int, dx: float, wavelength: float, n0: float,
+                    na_outer: float, na_inner: float) -> np.ndarray:
+    """Angular spectrum of a Bessel beam: a flat annulus k0 na_inner <= kt <=
+    k0 na_outer (natural DFT order, centred on pixel (0, 0))."""
+    _, _, ring = _annulus(nx, ny, dx, wavelength, na_outer, na_inner)
+    return ring.astype(np.complex128)
+
+
+def lattice_spectrum(nx: int, ny: int, dx: float, wavelength: float, n0: float,
+                     na_outer: float, na_inner: float, n_points: int = 6, sigma=0.02,
+                     phi0: float = 0.0) -> np.ndarray:
+    """Angular spectrum of a Bessel lattice: ``n_points`` plane waves whose
+    transverse wavevectors k_m = k0 na_r (cos phi_m, sin phi_m) lie on the
+    Bessel ring (na_r = (na_outer + na_inner) / 2, phi_m = phi0 + 2 pi m /
+    n_points), each a Gaussian spot exp(-((kx - kx_m) / (k0 sx))^2 - ((ky -
+    ky_m) / (k0 sy))^2) with (sx, sy) = sigma (NA units; a scalar for both),
+    cut to the annulus.  A small sy and a larger sx bound the lattice along x
+    into a sheet."""
+    k0 = 2 * np.pi / wavelength
+    kx, ky, ring = _annulus(nx, ny, dx, wavelength, na_outer, na_inner)
+    sx, sy = (sigma, sigma) if np.isscalar(sigma) else sigma
+    kr = k0 * 0.5 * (na_outer + na_inner)
+    spec = np.zeros((ny, nx))
+    for m in range(n_points):
+        ph = phi0 + 2 * np.pi * m / n_points
+        spec = spec + np.exp(-((kx - kr * np.cos(ph)) / (k0 * sx)) ** 2
+                             - ((ky - kr * np.sin(ph)) / (k0 * sy)) ** 2)
+    return np.where(ring, spec, 0.0).astype(np.complex128)
+
+
+def _centred_unit_field(spec, nx, ny, centre):
+    u = np.fft.ifft2(spec)
+    if centre is None:
+        centre = (ny // 2, nx // 2)
+    u = np.roll(u, (int(centre[0]), int(centre[1])), axis=(0, 1))
+    return (u / np.linalg.norm(u)).astype(np.complex64)
+
+
+def bessel_field(nx: int, ny: int, dx: float, wavelength: float, n0: float, na_outer: float,
+                 na_inner: float, centre=None) -> np.ndarray:
+    """complex64 Bessel beam centred on ``centre`` (default the grid centre),
+    ||u||_2 = 1."""
+    return _centred_unit_field(bessel_spectrum(nx, ny, dx, wavelength, n0, na_outer, na_inner),
+                               nx, ny, centre)
+
+
+def bessel_lattice_field(nx: int, ny: int, dx: float, wavelength: float, n0: float,
+                         na_outer: float, na_inner: float, n_points: int = 6, sigma=0.02,
+                         phi0: float = 0.0, centre=None) -> np.ndarray:
+    """complex64 Bessel lattice (``lattice_spectrum``), ||u||_2 = 1."""
+    spec = lattice_spectrum(nx, ny, dx, wavelength, n0, na_outer, na_inner, n_points, sigma,
+                            phi0)
+    return _centred_unit_field(spec, nx, ny, centre)
 
 
 # ---------------------------------------------------------------------------
