@@ -576,6 +576,58 @@ def zernike_rates(dev, dn, g, depth=512, pitch=32, n_modes=15, reps=3):
     return res
 
 
+def camera_rates(dev, dn, ls_intensity, g, half_depth=15, pitch=32, reps=2):
+    """One camera frame of the detection volume focused on its middle slice:
+    excitation from the timed light-sheet march (its intensity volume, back in
+    the detection frame), fluorophores where dn > 0.01, node PSFs on a pitch-32
+    grid at the 31 depths around focus (uneven batch marches of 8 depths, one
+    refocus readout each) and the spatially varying sum."""
+    import numpy as np
+    import torch
+    from paper_1706_02261_amd import imaging, psfs
+    opt = psfs.Optics(g.dx, g.dz, g.wavelength, g.n0, 0.6)
+    nz, ny, nx = dn.shape
+    f = nz // 2
+    exc = ls_intensity.permute(2, 1, 0).contiguous()     # [x][y][z] -> [z][y][x]
+    dens = (dn > 0.01).to(torch.float32)
+    run = lambda: imaging.camera_image(exc, dens, dn, f, pitch, opt, half_depth=half_depth)
+    img = run()
+    torch.cuda.synchronize(dev)
+    ts = []
+    for _ in range(reps):
+        a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        a.record()
+        img = run()
+        b.record()
+        torch.cuda.synchronize(dev)
+        ts.append(a.elapsed_time(b))
+    ms = float(np.median(ts))
+    # the image sum alone: 31 slabs through one depth's node PSFs
+    P = torch.rand((ny // pitch, nx // pitch, 32, 32), device=dev)
+    acc = torch.zeros((ny, nx), dtype=torch.float32, device=dev)
+    a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    a.record()
+    for z in range(2 * half_depth + 1):
+        imaging.camera_accumulate(acc, exc[f], P, pitch, density=dens[f])
+    b.record()
+    torch.cuda.synchronize(dev)
+    sum_ms = a.elapsed_time(b)
+    depths = 2 * half_depth + 1
+    n_psf = depths * (ny // pitch) * (nx // pitch)
+    # 32 x 32 PSF taps over ~9 nodes per output pixel (hat supports overlap)
+    macs = depths * nx * ny * 32 * 32 * 9
+    res = {"workload": f"{nx}x{ny} camera frame focused on slice {f} of the {nx}x{ny}x{nz} "
+                       f"volume: {depths} depths x {(ny // pitch) * (nx // pitch)} node PSFs "
+                       f"(pitch {pitch}), light-sheet excitation, fluorophores where dn > 0.01",
+           "frame_ms": round(ms, 2), "psfs_per_s": round(n_psf / (ms / 1e3), 1),
+           "image_sum_ms": round(sum_ms, 3),
+           "image_sum_fp32_tflops": round(2 * macs / (sum_ms / 1e3) / 1e12, 2),
+           "image_mean": round(float(img.mean()), 4)}
+    del exc, dens, P, acc, img
+    torch.cuda.empty_cache()
+    return res
+
+
 def phase_split(jobs, ws, stream, launch_ms):
     """One run of the timed launch with per-workgroup phase timers: mean and
     max over workgroups of each phase, in microseconds per step."""
@@ -756,6 +808,7 @@ def main():
         line["adjoint"] = adjoint_rate(dev)
         line["adaptive_optics"] = ao_rates(dev)
         line["zernike_map"] = zernike_rates(dev, jobs[0]["dn"], g, depth=g.steps // 2)
+        line["camera_frame"] = camera_rates(dev, jobs[0]["dn"], jobs[1]["intensity_out"], g)
         line["uneven_batch"] = batch_rate(dev)
     if not args.no_cpu_baseline:
         def gpu_first(steps):

@@ -338,6 +338,28 @@ int bpm_zernike_fit(const bpm_c64* pupil, int n_src, int crop, double dx, double
                     double na, int n_modes, float* coeffs_out, float* rms_out, void* workspace,
                     size_t workspace_bytes, void* hip_stream);
 
+/* Camera image of a fluorescent object (Fig. 1c; main-text paragraph on the
+ * light-sheet simulation: the spatially varying PSFs convolved with the
+ * fluorescent object give the image seen by the camera).  Fluorescence adds
+ * intensities; the slab of one depth, with emission E = excitation x density
+ * (density NULL: E = excitation), adds
+ *     image(x) += sum_{x'} E(x') sum_g phi_g(x') PSF_g(x - x'),
+ * PSF_g the crop x crop PSF of node g in the camera's focal plane (centre
+ * index crop/2 = the emitter), nodes on a pitch grid at pixel
+ * (pitch/2 + pitch i, pitch/2 + pitch j), phi_g the periodic bilinear hat
+ * weights max(0, 1 - |dy|/pitch) max(0, 1 - |dx|/pitch) (a partition of
+ * unity), periodic indices.
+ *   excitation, density [ny][nx] float32 (density may be NULL)
+ *   node_psfs  [ny/pitch][nx/pitch][crop][crop] float32
+ *   image      [ny][nx] float32, accumulated in place (must not alias the
+ *              other arrays)
+ * nx, ny multiples of 32; pitch divides both, at least twice (two nodes per
+ * period keep the weights a partition of unity); crop 16 or 32.  Every output
+ * pixel is summed by one thread in a fixed order (deterministic). */
+int bpm_camera_accumulate(const float* excitation, const float* density,
+                          const float* node_psfs, int nx, int ny, int pitch, int crop,
+                          float* image, void* hip_stream);
+
 /* Bytes of workspace for bpm_point_sources. */
 size_t bpm_point_sources_workspace_size(int nx, int ny);
 

@@ -43,7 +43,7 @@ EXPORTS = (
     "bpm_propagate_adapted", "bpm_slice_means",
     "bpm_guide_star_phase", "bpm_adam_step",
     "bpm_pupil_fields_workspace_size", "bpm_pupil_fields", "bpm_zernike_workspace_size",
-    "bpm_zernike_fit",
+    "bpm_zernike_fit", "bpm_camera_accumulate",
 )
 BPM_MARCH_AUTO = 0
 BPM_MARCH_ONE_PER_CU = 1
@@ -138,6 +138,8 @@ def _declare(L):
     L.bpm_zernike_workspace_size.restype = _Z
     L.bpm_zernike_fit.argtypes = [_V, _I, _I, _D, _D, _D, _I, _V, _V, _V, _Z, _V]
     L.bpm_zernike_fit.restype = _I
+    L.bpm_camera_accumulate.argtypes = [_V, _V, _V, _I, _I, _I, _I, _V, _V]
+    L.bpm_camera_accumulate.restype = _I
     L.bpm_psf_readout_workspace_size.argtypes = [_I, _I, _I]
     L.bpm_psf_readout_workspace_size.restype = _Z
     L.bpm_psf_readout.argtypes = [_V, _I, _I, _D, _D, _D, _D, _D, _I, _V, _I, _I, _I, _D, _V,

@@ -798,6 +798,29 @@ int bpm_zernike_fit(const bpm_c64* pupil, int n_src, int crop, double dx, double
     return BPM_OK;
 }
 
+int bpm_camera_accumulate(const float* excitation, const float* density,
+                          const float* node_psfs, int nx, int ny, int pitch, int crop,
+                          float* image, void* hip_stream) {
+    if (nx < 32 || ny < 32 || nx % 32 || ny % 32 || nx > (1 << 16) || ny > (1 << 16))
+        return fail(BPM_ERR_UNSUPPORTED_SIZE,
+                    "nx=%d ny=%d: sizes must be multiples of 32 in [32, 65536]", nx, ny);
+    if ((crop != 16 && crop != 32) || pitch < 2 || nx % pitch || ny % pitch ||
+        nx / pitch < 2 || ny / pitch < 2)
+        return fail(BPM_ERR_INVALID_ARG,
+                    "crop=%d must be 16 or 32 and pitch=%d >= 2 must divide nx and ny at "
+                    "least twice", crop, pitch);
+    if (!excitation || !node_psfs || !image)
+        return fail(BPM_ERR_INVALID_ARG, "excitation, node_psfs and image must be non-null");
+    if (!aligned(excitation, 4) || !aligned(node_psfs, 4) || !aligned(image, 4) ||
+        (density && !aligned(density, 4)))
+        return fail(BPM_ERR_INVALID_ARG, "misaligned array");
+    if (excitation == image || density == image)
+        return fail(BPM_ERR_INVALID_ARG, "image must not alias excitation or density");
+    return device_status(bpm::launch_camera(excitation, density, node_psfs, nx, ny, pitch, crop,
+                                            image, static_cast<hipStream_t>(hip_stream)),
+                         "camera image");
+}
+
 size_t bpm_point_sources_workspace_size(int nx, int ny) {
     if (!pow2_in_range(nx) || !pow2_in_range(ny)) return 0;
     return bpm::sources_bytes(nx, ny);

@@ -172,6 +172,10 @@ struct ZernikeArgs {
 size_t zernike_bytes(int crop, int n_modes);
 hipError_t launch_zernike_fit(const ZernikeArgs& a, void* ws, int* host_ok, hipStream_t s);
 
+// Camera image through spatially varying node PSFs (camera.hip).
+hipError_t launch_camera(const float* excitation, const float* density, const float* node_psfs,
+                         int nx, int ny, int pitch, int crop, float* image, hipStream_t s);
+
 // Multiplexed point-source input field (sources.hip).
 struct SourceArgs {
     const int* positions;  // device [n_src][2] (y, x)

@@ -31,7 +31,7 @@ __all__ = [
     "smoothed_noise", "point_source_spectrum", "point_source_field",
     "multiplexed_field", "jittered_grid", "light_sheet_field", "Geometry",
     "bessel_spectrum", "bessel_field", "lattice_spectrum", "bessel_lattice_field",
-    "perlin_noise", "perlin_phantom", "ao_workload",
+    "perlin_noise", "perlin_phantom", "ao_workload", "fluorophore_density",
     "config0", "config1", "config2_detection", "config2_light_sheet",
     "config3", "batch_job_specs", "ellipsoid_phantom", "surrogate_volume",
 ]
@@ -296,6 +296,28 @@ def light_sheet_field(nx: int, ny: int, dx: float, wavelength: float, n0: float,
     u = np.roll(np.fft.ifft2(spec), shift, axis=(0, 1))
     u /= np.linalg.norm(u)
     return u.astype(np.complex64)
+
+
+# ---------------------------------------------------------------------------
+# fluorophores
+
+def fluorophore_density(g: Geometry, n_nuclei: int, r_range=(1.5, 4.0), n_beads: int = 0,
+                        gen: np.random.Generator | None = None) -> np.ndarray:
+    """Synthetic fluorophore density float32 [steps][ny][nx]: labelled nuclei
+    (uniform density 1 inside spheres of radius r_range, centres anywhere in
+    the volume) and ``n_beads`` single-voxel beads of density 4."""
+    gen = rng(7, 0) if gen is None else gen
+    rho = np.zeros((g.steps, g.ny, g.nx), dtype=np.float32)
+    c = np.stack([gen.uniform(0, g.steps * g.dz, n_nuclei),
+                  gen.uniform(0, g.ny * g.dx, n_nuclei) - g.ny * g.dx / 2,
+                  gen.uniform(0, g.nx * g.dx, n_nuclei) - g.nx * g.dx / 2], axis=1)
+    add_spheres(rho, g.dx, g.dz, c, gen.uniform(*r_range, n_nuclei), np.ones(n_nuclei))
+    np.minimum(rho, 1.0, out=rho)
+    if n_beads:
+        idx = (gen.integers(0, g.steps, n_beads), gen.integers(0, g.ny, n_beads),
+               gen.integers(0, g.nx, n_beads))
+        rho[idx] = 4.0
+    return rho
 
 
 # ---------------------------------------------------------------------------

@@ -183,6 +183,14 @@ def test_helper_validation(L):
                              None) == B.BPM_ERR_INVALID_ARG and b"band" in L.bpm_last_error()
     assert L.bpm_zernike_fit(b.p, 2, 32, 0.2, 0.5, 0.6, 15, b.p, None, b.p, zws - 1,
                              None) == B.BPM_ERR_WORKSPACE
+    assert L.bpm_camera_accumulate(b.p, None, b.p, 100, 64, 4, 32, b.p,
+                                   None) == B.BPM_ERR_UNSUPPORTED_SIZE
+    assert L.bpm_camera_accumulate(b.p, None, b.p, 128, 64, 64, 32, b.p,
+                                   None) == B.BPM_ERR_INVALID_ARG      # one node row
+    assert L.bpm_camera_accumulate(b.p, None, b.p, 128, 128, 32, 24, b.p,
+                                   None) == B.BPM_ERR_INVALID_ARG
+    assert L.bpm_camera_accumulate(b.p, b.p, b.p, 128, 128, 32, 32, b.p,
+                                   None) == B.BPM_ERR_INVALID_ARG      # image aliases
 
 
 def test_surrogate_validation(L):

@@ -1,0 +1,73 @@
+"""GPU parity of the camera image (bpm_camera_accumulate and the imaging
+orchestration) with the FP64 oracle.
+
+* one slab through random node PSFs: grids with more nodes than a tile
+  reaches and with fewer (every node once), crops 16 and 32, a density
+  factor, accumulation into a non-zero image;
+* a whole camera frame: sources on a pitch-32 grid at seven depths around
+  the focal slice of a sphere phantom, marched, refocused to the focal plane
+  and summed with a light-sheet-like excitation and nuclei, against the
+  oracle's march, readout and sum.
+"""
+import numpy as np
+import pytest
+
+import oracle
+import synth
+from oracle import image as oim
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+LAM, N0, NA, DX, DZ = 0.5, 1.33, 0.6, 0.2, 0.2
+
+
+def to_gpu(a, dtype=np.float32):
+    return torch.from_numpy(np.ascontiguousarray(a, dtype)).cuda()
+
+
+def rel(a, b):
+    return float(np.linalg.norm(a - b) / np.linalg.norm(b))
+
+
+@pytest.mark.parametrize("nx,ny,pitch,crop", [(128, 128, 32, 32), (256, 128, 32, 32),
+                                              (64, 128, 16, 16), (96, 64, 32, 32),
+                                              (128, 128, 64, 32)])
+def test_camera_slab(nx, ny, pitch, crop):
+    from paper_1706_02261_amd import imaging
+    rng = np.random.default_rng(nx + ny + pitch)
+    exc = rng.uniform(0, 1, (ny, nx)).astype(np.float32)
+    dens = (rng.uniform(0, 1, (ny, nx)) > 0.7).astype(np.float32)
+    P = rng.uniform(0, 1, (ny // pitch, nx // pitch, crop, crop)).astype(np.float32)
+    img0 = rng.uniform(0, 1, (ny, nx)).astype(np.float32)
+    got = imaging.camera_accumulate(to_gpu(img0), to_gpu(exc), to_gpu(P), pitch,
+                                    density=to_gpu(dens)).cpu().numpy()
+    ref = oim.accumulate(img0, exc.astype(float) * dens, P, pitch)
+    assert rel(got, ref) <= 1e-6 and np.abs(got - ref).max() <= 1e-5 * ref.max()
+
+
+def test_camera_frame():
+    from paper_1706_02261_amd import imaging, psfs
+    n, nz, f, half, pitch = 128, 40, 20, 3, 32
+    g = synth.Geometry(n, n, nz, DX, DZ, LAM, N0)
+    dn = synth.sphere_phantom(g, 25, (1.0, 3.0), (0.0, 0.04), synth.rng(8, 0))
+    dens = synth.fluorophore_density(g, 12, gen=synth.rng(8, 1))
+    y = (np.arange(n) - n / 2) * DX
+    exc = np.broadcast_to(np.exp(-(y[None, :, None] / 3.0) ** 2), (nz, n, n)).astype(np.float32)
+    opt = psfs.Optics(DX, DZ, LAM, N0, NA)
+    got = imaging.camera_image(to_gpu(exc), to_gpu(dens), to_gpu(dn), f, pitch, opt,
+                               half_depth=half).cpu().numpy()
+    # oracle: clear-medium peak, node PSFs of each depth in the focal plane, sum
+    one = np.array([[n // 2, n // 2]])
+    u1 = oracle.point_sources(n, n, DX, LAM, N0, NA, 0.0, one)
+    peak = oracle.psf_readout(u1, DX, DZ, LAM, N0, NA, 0, one, planes=32, crop=32).max()
+    c = np.arange(pitch // 2, n, pitch)
+    src = np.stack(np.meshgrid(c, c, indexing="ij"), -1).reshape(-1, 2)
+    ref = np.zeros((n, n))
+    for z in range(f - half, f + half + 1):
+        u0 = oracle.point_sources(n, n, DX, LAM, N0, NA, 0.0, src)
+        ex, _ = oracle.bpm_forward(u0, dn[z:].astype(float), DX, DZ, LAM, N0, intensity=False)
+        P = oracle.psf_readout(ex, DX, DZ, LAM, N0, NA, nz - f, src, planes=1, crop=32) / peak
+        ref = oim.accumulate(ref, exc[z].astype(float) * dens[z], P.reshape(4, 4, 32, 32), pitch)
+    print(f"frame rel err {rel(got, ref):.2e}, image max {ref.max():.3f}")
+    assert rel(got, ref) <= 2e-5
