@@ -45,7 +45,8 @@ PAPER_GVS = 1024 ** 3 / 0.5 / 1e9  # < 500 ms for 1024^3 voxels, main text
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "march_1024cube_traffic.json")
 
 
-MARCH_SOURCES = ("fft.hpp", "mathx.hpp", "passes.hpp", "march_kernels.hpp", "march_x1024.hip")
+MARCH_SOURCES = ("fft.hpp", "mathx.hpp", "passes.hpp", "tiled.hpp", "march_kernels.hpp",
+                 "march_x1024.hip", "march.hip")
 
 
 def kernel_source_hash() -> str:
