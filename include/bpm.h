@@ -408,8 +408,13 @@ int psf_surrogate_infer(const void* weights_bf16, size_t weights_bytes,
  *                          per CU holding different fields, the field kept in
  *                          128-byte tiles between passes (two fields with
  *                          nx ny = 2^20 on a device of 256 CUs);
+ *   BPM_MARCH_SMALL_BLOCKS 64-thread workgroups, up to four per CU, twiddles in
+ *                          registers (nx, ny <= 1024): four times as many
+ *                          units per pass, for fields too small to give
+ *                          every CU a 256-thread unit;
  *   BPM_MARCH_AUTO         the built-in choice (tiled pair where eligible, two
- *                          per CU for several fields of sides >= 512, else one).
+ *                          per CU for several fields of sides >= 512, small
+ *                          blocks for one field of sides <= 512, else one).
  * All give bit-identical results.  A launch-shape tuner (the package's
  * tune.py) times the eligible kernels of a shape on the device and records
  * the fastest with bpm_set_march_variant. */
@@ -417,7 +422,8 @@ enum {
     BPM_MARCH_AUTO = 0,
     BPM_MARCH_ONE_PER_CU = 1,
     BPM_MARCH_TWO_PER_CU = 2,
-    BPM_MARCH_TILED_PAIR = 3
+    BPM_MARCH_TILED_PAIR = 3,
+    BPM_MARCH_SMALL_BLOCKS = 4
 };
 /* The kernel a march of this shape takes now (BPM_MARCH_ONE_PER_CU ..), or
  * BPM_ERR_INVALID_ARG for unsupported sizes or fields outside 1 .. 8. */

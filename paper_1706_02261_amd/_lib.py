@@ -49,6 +49,7 @@ BPM_MARCH_AUTO = 0
 BPM_MARCH_ONE_PER_CU = 1
 BPM_MARCH_TWO_PER_CU = 2
 BPM_MARCH_TILED_PAIR = 3
+BPM_MARCH_SMALL_BLOCKS = 4
 PHASE_TIMER_WORDS = 8 + 8 * 4096
 
 

@@ -81,7 +81,7 @@ int bpm_set_march_variant(int nx, int ny, int fields, int variant) {
     if (!pow2_in_range(nx) || !pow2_in_range(ny) || fields < 1 || fields > bpm::kMaxFields)
         return fail(BPM_ERR_INVALID_ARG, "nx=%d ny=%d fields=%d: sizes must be powers of two in "
                     "[32, 2048] and fields in [1, %d]", nx, ny, fields, bpm::kMaxFields);
-    if (variant < BPM_MARCH_AUTO || variant > BPM_MARCH_TILED_PAIR)
+    if (variant < BPM_MARCH_AUTO || variant > BPM_MARCH_SMALL_BLOCKS)
         return fail(BPM_ERR_INVALID_ARG, "variant=%d is not a BPM_MARCH_* value", variant);
     if (bpm::set_march_variant(nx, ny, fields, variant) != 0)
         return fail(BPM_ERR_INVALID_ARG, "variant %d cannot run %d x %d with %d field(s) on this "

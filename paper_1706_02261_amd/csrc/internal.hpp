@@ -17,7 +17,7 @@ inline size_t align_up(size_t v) { return (v + kAlign - 1) / kAlign * kAlign; }
 // (bpm_set_march_variant, e.g. from the launch-shape tuner) when eligible,
 // else the built-in choice.
 enum MarchVariant : int { kMarchAuto = 0, kMarchOnePerCu = 1, kMarchTwoPerCu = 2,
-                          kMarchTiledPair = 3 };
+                          kMarchTiledPair = 3, kMarchSmallBlocks = 4 };
 bool march_variant_eligible(int nx, int ny, int fields, int variant);
 int march_variant(int nx, int ny, int fields);
 int set_march_variant(int nx, int ny, int fields, int variant);  // 0 ok, -1 ineligible

@@ -57,14 +57,18 @@ struct MarchArgs {
 // the first is transformed).  OCC 2 (several fields) reads the twiddles from
 // tables in LDS instead, so that two workgroups fit one CU (two waves per
 // SIMD) and one workgroup's memory waits overlap the other's arithmetic.
-template <int NX, int NY, int OCC>
-__global__ __launch_bounds__(kBlock, OCC) void march_kernel(MarchArgs a) {
+// BLK = threads per workgroup: 256, or 64 (OCC 1 only) for small fields,
+// whose passes then have four times as many units, spread over four times
+// as many CUs (one wave per SIMD, up to four workgroups per CU).
+template <int NX, int NY, int OCC, int BLK = kBlock>
+__global__ __launch_bounds__(BLK, OCC) void march_kernel(MarchArgs a) {
+    static_assert(BLK == kBlock || OCC == 1, "small workgroups keep their twiddles in registers");
     extern __shared__ float2 smem[];
     PhaseTimers tm;
     tm.start(a.timers);
     const int G = gridDim.x, v = virtual_block();
-    const int rows_u = (a.ny + units_per_block<NX>() - 1) / units_per_block<NX>();
-    const int cols_u = (a.nx + units_per_block<NY>() - 1) / units_per_block<NY>();
+    const int rows_u = (a.ny + units_per_block<NX, BLK>() - 1) / units_per_block<NX, BLK>();
+    const int cols_u = (a.nx + units_per_block<NY, BLK>() - 1) / units_per_block<NY, BLK>();
     const int all_r = rows_u * a.fields, all_c = cols_u * a.fields;
     const size_t plane = (size_t)a.nx * a.ny;
     unsigned nbar = 0;
@@ -75,7 +79,7 @@ __global__ __launch_bounds__(kBlock, OCC) void march_kernel(MarchArgs a) {
     TwY twy;
     if constexpr (OCC == 1) {
         twx.load(a.twx, threadIdx.x % (NX / kR));
-        twy.load(a.twy, threadIdx.x / units_per_block<NY>());
+        twy.load(a.twy, threadIdx.x / units_per_block<NY, BLK>());
     } else {
         float2* tabx = smem + march_data_lds<NX, NY>() / sizeof(float2);
         float2* taby = tabx + LdsTwiddleTable<NX, kR>::size();
@@ -96,14 +100,14 @@ __global__ __launch_bounds__(kBlock, OCC) void march_kernel(MarchArgs a) {
     for (int u = v; u < all_r; u += G) {
         const int f = u % F;
         RowArgs ra{a.field_in[f], a.work[f], nullptr, nullptr, nullptr, nullptr, nullptr, a.k0dz};
-        row_unit<NX, kNaturalIn, kNoOps, kSpecOut>(u / F, a.ny, ra, d, twx, smem);
+        row_unit<NX, kNaturalIn, kNoOps, kSpecOut, BLK>(u / F, a.ny, ra, d, twx, smem);
     }
     tm.mark(kPhHead);
     // a workgroup with a single row unit fetches its dn slice during the column pass
     const bool one_row_unit = all_r <= G;
     const int vv = v < all_r ? v : 0;
     for (int j = 0; j < a.steps; ++j) {
-        if (one_row_unit) load_dn<NX>(d, vv / F, a.ny, a.dn[vv % F] + j * plane);
+        if (one_row_unit) load_dn<NX, BLK>(d, vv / F, a.ny, a.dn[vv % F] + j * plane);
         tm.mark(kPhRow);
         grid_sync(a.counter, ++nbar, abort, a.status, a.limit, tm);
         for (int u = v; u < all_c; u += PAIR * G) {
@@ -111,13 +115,13 @@ __global__ __launch_bounds__(kBlock, OCC) void march_kernel(MarchArgs a) {
             const bool two = PAIR == 2 && u2 < all_c;
             const int f1 = u % F, f2 = u2 % F;
             float2 va[kR], ha[kR], vb[kR], hb[kR];
-            col_load<NY>(u / F, a.nx, a.work[f1], a.H, va, ha);
-            if (two) col_load<NY>(u2 / F, a.nx, a.work[f2], a.H, vb, hb);
-            col_body<NY, false>(u / F, a.nx, a.work[f1], twy, smem, nullptr, nullptr, nullptr, va,
-                                ha);
+            col_load<NY, BLK>(u / F, a.nx, a.work[f1], a.H, va, ha);
+            if (two) col_load<NY, BLK>(u2 / F, a.nx, a.work[f2], a.H, vb, hb);
+            col_body<NY, false, BLK>(u / F, a.nx, a.work[f1], twy, smem, nullptr, nullptr, nullptr,
+                                     va, ha);
             if (two)
-                col_body<NY, false>(u2 / F, a.nx, a.work[f2], twy, smem, nullptr, nullptr,
-                                    nullptr, vb, hb);
+                col_body<NY, false, BLK>(u2 / F, a.nx, a.work[f2], twy, smem, nullptr, nullptr,
+                                         nullptr, vb, hb);
         }
         tm.mark(kPhCol);
         grid_sync(a.counter, ++nbar, abort, a.status, a.limit, tm);
@@ -128,27 +132,28 @@ __global__ __launch_bounds__(kBlock, OCC) void march_kernel(MarchArgs a) {
             const int f2 = u2 % F, r2 = two ? u2 / F : 0;
             float2 va[kR], vb[kR];
             float db[kR];
-            row_load<NX, kSpecIn>(r1, a.ny, a.work[f1], va);
-            if (!one_row_unit) load_dn<NX>(d, r1, a.ny, a.dn[f1] + j * plane);
+            row_load<NX, kSpecIn, BLK>(r1, a.ny, a.work[f1], va);
+            if (!one_row_unit) load_dn<NX, BLK>(d, r1, a.ny, a.dn[f1] + j * plane);
             if (two) {
-                row_load<NX, kSpecIn>(r2, a.ny, a.work[f2], vb);
-                load_dn<NX>(db, r2, a.ny, a.dn[f2] + j * plane);
+                row_load<NX, kSpecIn, BLK>(r2, a.ny, a.work[f2], vb);
+                load_dn<NX, BLK>(db, r2, a.ny, a.dn[f2] + j * plane);
             }
             const RowArgs ra{a.work[f1], a.work[f1],
                              a.inten[f1] ? a.inten[f1] + j * plane : nullptr, nullptr, nullptr,
                              nullptr, nullptr, a.k0dz};
             if (j + 1 < a.steps)
-                row_body<NX, kSpecIn, kScreen, kSpecOut>(r1, a.ny, ra, d, twx, smem, va);
+                row_body<NX, kSpecIn, kScreen, kSpecOut, BLK>(r1, a.ny, ra, d, twx, smem, va);
             else
-                row_body<NX, kSpecIn, kScreen, kNaturalOut>(r1, a.ny, ra, d, twx, smem, va);
+                row_body<NX, kSpecIn, kScreen, kNaturalOut, BLK>(r1, a.ny, ra, d, twx, smem, va);
             if (two) {
                 const RowArgs rb{a.work[f2], a.work[f2],
                                  a.inten[f2] ? a.inten[f2] + j * plane : nullptr, nullptr,
                                  nullptr, nullptr, nullptr, a.k0dz};
                 if (j + 1 < a.steps)
-                    row_body<NX, kSpecIn, kScreen, kSpecOut>(r2, a.ny, rb, db, twx, smem, vb);
+                    row_body<NX, kSpecIn, kScreen, kSpecOut, BLK>(r2, a.ny, rb, db, twx, smem, vb);
                 else
-                    row_body<NX, kSpecIn, kScreen, kNaturalOut>(r2, a.ny, rb, db, twx, smem, vb);
+                    row_body<NX, kSpecIn, kScreen, kNaturalOut, BLK>(r2, a.ny, rb, db, twx, smem,
+                                                                     vb);
             }
         }
     }
@@ -574,6 +579,13 @@ hipError_t launch_forward_x(const MarchArgs& a, hipStream_t s) {
                     reinterpret_cast<const void*>(&march_kernel<NX, NY, 2>),
                     dim3(persistent_grid<NX, NY>(a.nx, a.ny, a.fields, 2)), dim3(kBlock), args,
                     (unsigned)(march_data_lds<NX, NY>() + march_twiddle_lds<NX, NY>()), s);
+        }
+        if constexpr (NX <= 1024 && NY <= 1024) {
+            if (a.variant == kMarchSmallBlocks)
+                return hipLaunchCooperativeKernel(
+                    reinterpret_cast<const void*>(&march_kernel<NX, NY, 1, 64>),
+                    dim3(persistent_grid<NX, NY, 64>(a.nx, a.ny, a.fields, 4)), dim3(64), args,
+                    (unsigned)persistent_lds<NX, NY, 64>(), s);
         }
         if (a.variant != kMarchOnePerCu) return hipErrorInvalidConfiguration;
         return hipLaunchCooperativeKernel(reinterpret_cast<const void*>(&march_kernel<NX, NY, 1>),

@@ -2,7 +2,8 @@
 
 For each shape (nx, ny, lockstep fields) the library offers one or more
 kernels (include/bpm.h, BPM_MARCH_*): one workgroup per CU with register
-twiddles, two per CU with LDS twiddles, and the two-field tiled march.  They
+twiddles, two per CU with LDS twiddles, the two-field tiled march, and
+64-thread workgroups for small fields.  They
 give identical results; which is fastest depends on the shape and the device.
 ``tune`` times every eligible kernel of each shape on the current device (a
 short march of random fields, median of a few launches timed with events on
@@ -24,7 +25,7 @@ from . import bpm as _bpm
 from ._lib import check, lib
 
 VARIANTS = {_lib.BPM_MARCH_ONE_PER_CU: "one_per_cu", _lib.BPM_MARCH_TWO_PER_CU: "two_per_cu",
-            _lib.BPM_MARCH_TILED_PAIR: "tiled_pair"}
+            _lib.BPM_MARCH_TILED_PAIR: "tiled_pair", _lib.BPM_MARCH_SMALL_BLOCKS: "small_blocks"}
 
 
 def cache_path() -> str:

@@ -314,8 +314,11 @@ def test_march_variant_choice_and_overrides(L):
     assert L.bpm_march_variant_eligible(512, 1024, 3, B.BPM_MARCH_TWO_PER_CU) == 1
     assert L.bpm_march_variant_eligible(512, 512, 9, B.BPM_MARCH_ONE_PER_CU) == 0
     assert L.bpm_march_variant_eligible(512, 512, 1, 7) == 0
+    assert L.bpm_march_variant_eligible(1024, 128, 3, B.BPM_MARCH_SMALL_BLOCKS) == 1
+    assert L.bpm_march_variant_eligible(2048, 512, 1, B.BPM_MARCH_SMALL_BLOCKS) == 0
     assert L.bpm_march_variant(100, 64, 1) == B.BPM_ERR_INVALID_ARG
-    assert L.bpm_march_variant(512, 512, 1) == B.BPM_MARCH_ONE_PER_CU
+    assert L.bpm_march_variant(512, 512, 1) == B.BPM_MARCH_SMALL_BLOCKS
+    assert L.bpm_march_variant(1024, 1024, 1) == B.BPM_MARCH_ONE_PER_CU
     assert L.bpm_march_variant(512, 512, 2) == B.BPM_MARCH_TWO_PER_CU
     assert L.bpm_set_march_variant(512, 512, 2, B.BPM_MARCH_ONE_PER_CU) == B.BPM_OK
     assert L.bpm_march_variant(512, 512, 2) == B.BPM_MARCH_ONE_PER_CU

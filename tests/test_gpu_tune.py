@@ -16,7 +16,9 @@ def jobs_of(nx, ny, fields, steps, seed):
                  dx=0.2, dz=0.2, wavelength=0.5, n0=1.33) for _ in range(fields)]
 
 
-@pytest.mark.parametrize("shape", [(1024, 1024, 2), (512, 512, 3), (2048, 512, 2), (256, 128, 1)])
+@pytest.mark.parametrize("shape", [(1024, 1024, 2), (512, 512, 3), (2048, 512, 2), (256, 128, 1),
+                                   (128, 128, 1), (32, 1024, 1), (1024, 32, 2), (64, 64, 5),
+                                   (1024, 1024, 1)])
 def test_every_kernel_of_a_shape_gives_the_same_bits(shape):
     import paper_1706_02261_amd as bpm
     from paper_1706_02261_amd import tune
