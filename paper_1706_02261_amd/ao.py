@@ -199,6 +199,8 @@ def speckle_autocorrelation(intensity: torch.Tensor, max_lag: int):
 
 def mean_free_paths(exit_plane_wave: torch.Tensor) -> float:
     """-ln |<u_N>|^2 of a unit plane wave: the depth in scattering mean free
-    paths (the ballistic power decays as exp(-z / l_s))."""
+    paths (the ballistic power decays as exp(-z / l_s)); inf when no
+    ballistic light is left."""
     import math
-    return -math.log(float(exit_plane_wave.mean().abs()) ** 2)
+    p = float(exit_plane_wave.mean().abs()) ** 2
+    return math.inf if p == 0.0 else -math.log(p)

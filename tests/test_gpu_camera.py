@@ -71,3 +71,14 @@ def test_camera_frame():
         ref = oim.accumulate(ref, exc[z].astype(float) * dens[z], P.reshape(4, 4, 32, 32), pitch)
     print(f"frame rel err {rel(got, ref):.2e}, image max {ref.max():.3f}")
     assert rel(got, ref) <= 2e-5
+
+
+def test_camera_zero_emission_leaves_the_image():
+    from paper_1706_02261_amd import imaging
+    rng = np.random.default_rng(3)
+    img0 = rng.uniform(0, 1, (64, 96)).astype(np.float32)
+    P = rng.uniform(0, 1, (2, 3, 32, 32)).astype(np.float32)
+    img = to_gpu(img0)
+    imaging.camera_accumulate(img, to_gpu(np.ones((64, 96))), to_gpu(P), 32,
+                              density=to_gpu(np.zeros((64, 96))))
+    assert np.array_equal(img.cpu().numpy(), img0)
