@@ -35,9 +35,9 @@ __global__ void batch_zero_kernel(unsigned* q, int words) {
         q[i] = 0u;
 }
 
-// One item covers up to kUnitsPerItem consecutive units of one pass: the
-// second unit's loads are issued before the first unit is transformed, and
-// the queue and completion-counter round trips are shared.
+// One item covers up to kUnitsPerItem consecutive units of one pass, two at a
+// time (the second unit's loads are issued before the first unit is
+// transformed); the queue and completion-counter round trips are shared.
 // The per-size bodies are separate functions (not inlined into the item loop):
 // with every transform length inlined into one kernel the compiler keeps each
 // length's loop-invariant addresses live at once and spills.  Their pointer
@@ -58,38 +58,40 @@ __device__ __attribute__((noinline)) void batch_row(const g_float2* field_in, g_
     OpaqueTwiddles<NX, kR> tw;
     tw.load((const float2*)twx, threadIdx.x % (NX / kR));
     const int units = (ny + units_per_block<NX>() - 1) / units_per_block<NX>();
-    const int u0 = item * kUnitsPerItem, u1 = u0 + 1;
-    const bool two = u1 < units;
-    float d0[kR], d1[kR];
-    float2 va[kR], vb[kR];
-    if (pass == 0) {
-#pragma unroll
-        for (int i = 0; i < kR; ++i) d0[i] = 0.f;
-        const RowArgs ra{(const float2*)field_in, work, nullptr, nullptr, nullptr, nullptr,
-                         nullptr, k0dz};
-        row_load<NX, kNaturalIn>(u0, ny, ra.src, va);
-        if (two) row_load<NX, kNaturalIn>(u1, ny, ra.src, vb);
-        row_body<NX, kNaturalIn, kNoOps, kSpecOut>(u0, ny, ra, d0, tw, smem, va);
-        if (two) row_body<NX, kNaturalIn, kNoOps, kSpecOut>(u1, ny, ra, d0, tw, smem, vb);
-        return;
-    }
     const int s = pass / 2 - 1;
     const size_t plane = (size_t)nx * ny;
-    const float* dns = (const float*)dn + s * plane;
-    const RowArgs ra{work, work, inten ? (float*)inten + s * plane : nullptr, nullptr, nullptr,
-                     nullptr, nullptr, k0dz};
-    row_load<NX, kSpecIn>(u0, ny, ra.src, va);
-    load_dn<NX>(d0, u0, ny, dns);
-    if (two) {
-        row_load<NX, kSpecIn>(u1, ny, ra.src, vb);
-        load_dn<NX>(d1, u1, ny, dns);
-    }
-    if (s + 1 < steps) {
-        row_body<NX, kSpecIn, kScreen, kSpecOut>(u0, ny, ra, d0, tw, smem, va);
-        if (two) row_body<NX, kSpecIn, kScreen, kSpecOut>(u1, ny, ra, d1, tw, smem, vb);
-    } else {
-        row_body<NX, kSpecIn, kScreen, kNaturalOut>(u0, ny, ra, d0, tw, smem, va);
-        if (two) row_body<NX, kSpecIn, kScreen, kNaturalOut>(u1, ny, ra, d1, tw, smem, vb);
+    for (int u0 = item * kUnitsPerItem; u0 < units && u0 < (item + 1) * kUnitsPerItem; u0 += 2) {
+        const int u1 = u0 + 1;
+        const bool two = u1 < units;
+        float d0[kR], d1[kR];
+        float2 va[kR], vb[kR];
+        if (pass == 0) {
+#pragma unroll
+            for (int i = 0; i < kR; ++i) d0[i] = 0.f;
+            const RowArgs ra{(const float2*)field_in, work, nullptr, nullptr, nullptr, nullptr,
+                             nullptr, k0dz};
+            row_load<NX, kNaturalIn>(u0, ny, ra.src, va);
+            if (two) row_load<NX, kNaturalIn>(u1, ny, ra.src, vb);
+            row_body<NX, kNaturalIn, kNoOps, kSpecOut>(u0, ny, ra, d0, tw, smem, va);
+            if (two) row_body<NX, kNaturalIn, kNoOps, kSpecOut>(u1, ny, ra, d0, tw, smem, vb);
+            continue;
+        }
+        const float* dns = (const float*)dn + s * plane;
+        const RowArgs ra{work, work, inten ? (float*)inten + s * plane : nullptr, nullptr,
+                         nullptr, nullptr, nullptr, k0dz};
+        row_load<NX, kSpecIn>(u0, ny, ra.src, va);
+        load_dn<NX>(d0, u0, ny, dns);
+        if (two) {
+            row_load<NX, kSpecIn>(u1, ny, ra.src, vb);
+            load_dn<NX>(d1, u1, ny, dns);
+        }
+        if (s + 1 < steps) {
+            row_body<NX, kSpecIn, kScreen, kSpecOut>(u0, ny, ra, d0, tw, smem, va);
+            if (two) row_body<NX, kSpecIn, kScreen, kSpecOut>(u1, ny, ra, d1, tw, smem, vb);
+        } else {
+            row_body<NX, kSpecIn, kScreen, kNaturalOut>(u0, ny, ra, d0, tw, smem, va);
+            if (two) row_body<NX, kSpecIn, kScreen, kNaturalOut>(u1, ny, ra, d1, tw, smem, vb);
+        }
     }
 }
 
@@ -103,13 +105,15 @@ __device__ __attribute__((noinline)) void batch_col(g_float2* work_g, const g_fl
     OpaqueTwiddles<NY, kR> tw;
     tw.load((const float2*)twy, threadIdx.x / units_per_block<NY>());
     const int units = (nx + units_per_block<NY>() - 1) / units_per_block<NY>();
-    const int u0 = item * kUnitsPerItem, u1 = u0 + 1;
-    const bool two = u1 < units;
-    float2 va[kR], ha[kR], vb[kR], hb[kR];
-    col_load<NY>(u0, nx, work, H, va, ha);
-    if (two) col_load<NY>(u1, nx, work, H, vb, hb);
-    col_body<NY, false>(u0, nx, work, tw, smem, nullptr, nullptr, nullptr, va, ha);
-    if (two) col_body<NY, false>(u1, nx, work, tw, smem, nullptr, nullptr, nullptr, vb, hb);
+    for (int u0 = item * kUnitsPerItem; u0 < units && u0 < (item + 1) * kUnitsPerItem; u0 += 2) {
+        const int u1 = u0 + 1;
+        const bool two = u1 < units;
+        float2 va[kR], ha[kR], vb[kR], hb[kR];
+        col_load<NY>(u0, nx, work, H, va, ha);
+        if (two) col_load<NY>(u1, nx, work, H, vb, hb);
+        col_body<NY, false>(u0, nx, work, tw, smem, nullptr, nullptr, nullptr, va, ha);
+        if (two) col_body<NY, false>(u1, nx, work, tw, smem, nullptr, nullptr, nullptr, vb, hb);
+    }
 }
 
 __global__ __launch_bounds__(kBlock) void batch_kernel(const BatchJob* __restrict__ jobs,

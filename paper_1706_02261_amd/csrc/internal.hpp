@@ -126,7 +126,7 @@ struct BatchSeg {
     int job, pass, first, count, need;
 };
 int batch_queue_words(int n_jobs);
-constexpr int kUnitsPerItem = 2;  // units of one pass per work item
+constexpr int kUnitsPerItem = 4;  // units of one pass per work item (even)
 int row_units(int nx, int ny);
 int col_units(int nx, int ny);
 int row_items(int nx, int ny);  // work items of one row pass
