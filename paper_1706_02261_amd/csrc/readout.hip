@@ -271,25 +271,31 @@ __device__ inline double factorial_d(int n) {
     return f;
 }
 
-// Noll-normalised Zernike polynomial Z_j(rho, theta)
-__device__ double zernike_d(int j, double rho, double theta) {
-    int n, m;
-    noll_nm(j, n, m);
-    const int am = m < 0 ? -m : m;
-    double r = 0.0;
-    for (int s = 0; s <= (n - am) / 2; ++s) {
-        const double c = ((s & 1) ? -1.0 : 1.0) * factorial_d(n - s) /
-                         (factorial_d(s) * factorial_d((n + am) / 2 - s) *
-                          factorial_d((n - am) / 2 - s));
-        r += c * pow(rho, (double)(n - 2 * s));
+// Noll-normalised Zernike polynomials Z_1 .. Z_J at one point, into z[]
+// (radial powers by repeated multiplication; n <= 6 for J <= 28)
+__device__ void zernike_all(int J, double rho, double theta, double* z) {
+    double rp[7];
+    rp[0] = 1.0;
+    for (int k = 1; k < 7; ++k) rp[k] = rp[k - 1] * rho;
+    for (int j = 0; j < J; ++j) {
+        int n, m;
+        noll_nm(j + 1, n, m);
+        const int am = m < 0 ? -m : m;
+        double r = 0.0;
+        for (int s = 0; s <= (n - am) / 2; ++s)
+            r += ((s & 1) ? -1.0 : 1.0) * factorial_d(n - s) /
+                 (factorial_d(s) * factorial_d((n + am) / 2 - s) * factorial_d((n - am) / 2 - s)) *
+                 rp[n - 2 * s];
+        z[j] = m == 0 ? sqrt((double)(n + 1)) * r
+                      : sqrt(2.0 * (n + 1)) * r * (m > 0 ? cos(am * theta) : sin(am * theta));
     }
-    if (m == 0) return sqrt((double)(n + 1)) * r;
-    return sqrt(2.0 * (n + 1)) * r * (m > 0 ? cos(am * theta) : sin(am * theta));
 }
 
 // One workgroup: the basis Z [J][C*C] on the disc (zero outside) and the
 // least-squares operator P = (Z^T Z)^-1 Z^T [J][C*C], both float; Zd is a
-// double scratch [J][C*C].  R2 = (NA C dx / lambda)^2, R its root.
+// double scratch [J][C*C].  R = NA C dx / lambda.  The Gram matrix is summed
+// over chunks of kAbBlock samples staged in LDS (one sample per thread) and
+// inverted by the whole workgroup (Gauss-Jordan, one pivot per round).
 template <int C>
 __global__ __launch_bounds__(kAbBlock) void zernike_basis_kernel(int J, double R,
                                                                  double* __restrict__ Zd,
@@ -297,65 +303,103 @@ __global__ __launch_bounds__(kAbBlock) void zernike_basis_kernel(int J, double R
                                                                  float* __restrict__ Pf,
                                                                  int* __restrict__ ok) {
     constexpr int CC = C * C;
-    __shared__ double G[kMaxZernike * kMaxZernike];
-    __shared__ double Gi[kMaxZernike * kMaxZernike];
-    for (int i = threadIdx.x; i < CC; i += kAbBlock) {
+    constexpr int W2 = 2 * kMaxZernike;
+    __shared__ double A[kMaxZernike * W2];  // [G | I] -> [I | G^-1] by Gauss-Jordan
+    __shared__ double zs[kAbBlock * kMaxZernike];
+    __shared__ int s_bad;
+    const int npairs = J * (J + 1) / 2;
+    double gacc[2] = {0.0, 0.0};  // pairs threadIdx.x and threadIdx.x + kAbBlock
+    int pa[2], pb[2];
+    for (int q = 0; q < 2; ++q) {
+        int p = threadIdx.x + q * kAbBlock, a = 0;
+        while (p > a) {  // pair p = (a, b), b <= a, in row-major lower-triangle order
+            p -= a + 1;
+            ++a;
+        }
+        pa[q] = a;
+        pb[q] = p;
+    }
+    for (int c0 = 0; c0 < CC; c0 += kAbBlock) {
+        const int i = c0 + threadIdx.x;
+        double z[kMaxZernike];
         const int l = i / C, m = i % C;
         const int ls = l < C / 2 ? l : l - C, ms = m < C / 2 ? m : m - C;
-        const bool in = (double)(ls * ls + ms * ms) <= R * R;
-        const double rho = sqrt((double)(ls * ls + ms * ms)) / R;
-        const double th = atan2((double)ls, (double)ms);
-        for (int j = 0; j < J; ++j) Zd[(size_t)j * CC + i] = in ? zernike_d(j + 1, rho, th) : 0.0;
-    }
-    __syncthreads();
-    for (int p = threadIdx.x; p < J * J; p += kAbBlock) {
-        const int a = p / J, b = p % J;
-        double acc = 0.0;
-        if (b <= a)
-            for (int i = 0; i < CC; ++i) acc += Zd[(size_t)a * CC + i] * Zd[(size_t)b * CC + i];
-        G[p] = acc;
-    }
-    __syncthreads();
-    if (threadIdx.x == 0) {
-        // Cholesky G = L L^T in the lower triangle, then Gi = G^-1 column by column
-        int good = 1;
-        for (int c = 0; c < J && good; ++c) {
-            double d = G[c * J + c];
-            for (int k = 0; k < c; ++k) d -= G[c * J + k] * G[c * J + k];
-            if (!(d > 0.0)) {
-                good = 0;
-                break;
-            }
-            d = sqrt(d);
-            G[c * J + c] = d;
-            for (int r = c + 1; r < J; ++r) {
-                double v = G[r * J + c];
-                for (int k = 0; k < c; ++k) v -= G[r * J + k] * G[c * J + k];
-                G[r * J + c] = v / d;
+        const bool in = i < CC && (double)(ls * ls + ms * ms) <= R * R;
+        if (in)
+            zernike_all(J, sqrt((double)(ls * ls + ms * ms)) / R, atan2((double)ls, (double)ms), z);
+        for (int j = 0; j < J; ++j) {
+            const double v = in ? z[j] : 0.0;
+            zs[threadIdx.x * kMaxZernike + j] = v;
+            if (i < CC) {
+                Zd[(size_t)j * CC + i] = v;
+                Zf[(size_t)j * CC + i] = (float)v;
             }
         }
-        for (int col = 0; col < J && good; ++col) {
-            double y[kMaxZernike];
-            for (int r = 0; r < J; ++r) {
-                double v = (r == col) ? 1.0 : 0.0;
-                for (int k = 0; k < r; ++k) v -= G[r * J + k] * y[k];
-                y[r] = v / G[r * J + r];
-            }
-            for (int r = J - 1; r >= 0; --r) {
-                double v = y[r];
-                for (int k = r + 1; k < J; ++k) v -= G[k * J + r] * Gi[k * J + col];
-                Gi[r * J + col] = v / G[r * J + r];
+        __syncthreads();
+        for (int q = 0; q < 2; ++q) {
+            if (threadIdx.x + q * kAbBlock < npairs) {
+                double acc = gacc[q];
+                for (int t = 0; t < kAbBlock; ++t)
+                    acc += zs[t * kMaxZernike + pa[q]] * zs[t * kMaxZernike + pb[q]];
+                gacc[q] = acc;
             }
         }
-        *ok = good;
+        __syncthreads();
+    }
+    for (int e = threadIdx.x; e < J * W2; e += kAbBlock) {
+        const int r = e / W2, c = e % W2;
+        A[r * W2 + c] = c >= J ? (c - J == r ? 1.0 : 0.0) : 0.0;
+    }
+    if (threadIdx.x == 0) s_bad = 0;
+    __syncthreads();
+    for (int q = 0; q < 2; ++q) {
+        if (threadIdx.x + q * kAbBlock < npairs) {
+            A[pa[q] * W2 + pb[q]] = gacc[q];
+            A[pb[q] * W2 + pa[q]] = gacc[q];
+        }
+    }
+    // Gauss-Jordan on [G | I]: G is symmetric positive definite, so the
+    // pivots of the unpivoted elimination are positive exactly when the
+    // basis is not singular on the disc
+    constexpr int PER = (kMaxZernike * W2 + kAbBlock - 1) / kAbBlock;
+    for (int k = 0; k < J; ++k) {
+        __syncthreads();
+        const double piv = A[k * W2 + k];
+        if (!(piv > 0.0)) {
+            if (threadIdx.x == 0) s_bad = 1;
+            break;
+        }
+        double ark[PER], akc[PER], arc[PER];
+#pragma unroll
+        for (int q = 0; q < PER; ++q) {
+            const int e = threadIdx.x + q * kAbBlock;
+            if (e < J * W2) {
+                const int r = e / W2, c = e % W2;
+                ark[q] = A[r * W2 + k];
+                akc[q] = A[k * W2 + c];
+                arc[q] = A[r * W2 + c];
+            }
+        }
+        __syncthreads();
+#pragma unroll
+        for (int q = 0; q < PER; ++q) {
+            const int e = threadIdx.x + q * kAbBlock;
+            if (e < J * W2) {
+                const int r = e / W2, c = e % W2;
+                const double t = akc[q] / piv;
+                A[r * W2 + c] = r == k ? t : arc[q] - ark[q] * t;
+            }
+        }
     }
     __syncthreads();
+    if (threadIdx.x == 0) *ok = s_bad ? 0 : 1;
     for (int i = threadIdx.x; i < CC; i += kAbBlock) {
+        double z[kMaxZernike];
+        for (int k = 0; k < J; ++k) z[k] = Zd[(size_t)k * CC + i];
         for (int j = 0; j < J; ++j) {
             double acc = 0.0;
-            for (int k = 0; k < J; ++k) acc += Gi[j * J + k] * Zd[(size_t)k * CC + i];
+            for (int k = 0; k < J; ++k) acc += A[j * W2 + J + k] * z[k];
             Pf[(size_t)j * CC + i] = (float)acc;
-            Zf[(size_t)j * CC + i] = (float)Zd[(size_t)j * CC + i];
         }
     }
 }
