@@ -128,6 +128,14 @@ typedef struct {
     double dx, dz, wavelength, n0;
     bpm_c64* field_out;
     float* intensity_out;
+    /* Steps at the start that propagate in the background medium: for
+     * j < clear_steps the screen is skipped (dn[j] is taken as 0 and never
+     * read).  0 .. steps.  With a source entered clear_steps slices early as
+     * the clear-medium field that focuses clear_steps dz downstream, the job
+     * leaves the volume exactly as the source marched from slice clear_steps
+     * (free-space steps compose), so sources of different depths can march
+     * in one lockstep launch of equal-length jobs. */
+    int clear_steps;
 } bpm_job;
 
 /* Bytes of workspace for bpm_propagate_batch over `jobs` (host array). */

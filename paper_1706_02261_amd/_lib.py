@@ -65,7 +65,8 @@ class Job(ctypes.Structure):
                 ("nx", ctypes.c_int), ("ny", ctypes.c_int), ("steps", ctypes.c_int),
                 ("dx", ctypes.c_double), ("dz", ctypes.c_double),
                 ("wavelength", ctypes.c_double), ("n0", ctypes.c_double),
-                ("field_out", ctypes.c_void_p), ("intensity_out", ctypes.c_void_p)]
+                ("field_out", ctypes.c_void_p), ("intensity_out", ctypes.c_void_p),
+                ("clear_steps", ctypes.c_int)]
 
 
 _lib = None

@@ -355,7 +355,8 @@ def _batch_table(jobs):
             _need(inten, f"jobs[{i}].intensity_out", torch.float32, (steps, ny, nx))
         arr[i] = _lib.Job(f.data_ptr(), d.data_ptr(), nx, ny, steps, float(j["dx"]),
                           float(j["dz"]), float(j["wavelength"]), float(j["n0"]),
-                          out.data_ptr(), 0 if inten is None else inten.data_ptr())
+                          out.data_ptr(), 0 if inten is None else inten.data_ptr(),
+                          int(j.get("clear_steps", 0)))
         results.append((out, inten))
         dev = f.device
     need = lib().bpm_batch_workspace_size(arr, len(jobs))
@@ -368,8 +369,9 @@ def propagate_batch(jobs, ws: torch.Tensor | None = None, stream=None):
     """Run an uneven batch of marches in one persistent launch.
 
     ``jobs``: sequence of dicts with keys field, dn, dx, dz, wavelength, n0 and
-    optional out, intensity (bool, default True), intensity_out.  Returns a
-    list of (field_out, intensity) per job."""
+    optional out, intensity (bool, default True), intensity_out and
+    clear_steps (leading steps in the background medium, whose dn slices are
+    not read; default 0).  Returns a list of (field_out, intensity) per job."""
     if len(jobs) == 0:
         return []
     arr, results, need, dev = _batch_table(jobs)

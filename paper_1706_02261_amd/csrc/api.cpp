@@ -248,6 +248,7 @@ unsigned long long batch_key(const bpm_job* jobs, int n, const void* ws) {
         mix(&j.nx, sizeof j.nx);
         mix(&j.ny, sizeof j.ny);
         mix(&j.steps, sizeof j.steps);
+        mix(&j.clear_steps, sizeof j.clear_steps);
         mix(&j.dx, sizeof j.dx);
         mix(&j.dz, sizeof j.dz);
         mix(&j.wavelength, sizeof j.wavelength);
@@ -295,6 +296,9 @@ int check_batch(const bpm_job* jobs, int n) {
             return fail(rc, "job %d: %s", i, g_last_error.c_str());
         if (j.intensity_out && !aligned(j.intensity_out, 4))
             return fail(BPM_ERR_INVALID_ARG, "job %d: intensity_out must be 4-byte aligned", i);
+        if (j.clear_steps < 0 || j.clear_steps > j.steps)
+            return fail(BPM_ERR_INVALID_ARG, "job %d: clear_steps=%d must be in [0, steps=%d]",
+                        i, j.clear_steps, j.steps);
         if (j.steps > 0)
             items += (long)bpm::row_items(j.nx, j.ny) * (j.steps + 1) +
                      (long)bpm::col_items(j.nx, j.ny) * j.steps;
@@ -321,7 +325,8 @@ int batch_tables(const bpm_job* jobs, int n_jobs, char* ws, const BatchLayout& L
         const bpm::Plan p = bpm::plan_carve(ws + L.plan_off[i], j.nx, j.ny);
         dj[i] = bpm::BatchJob{j.field_in, j.dn, j.field_out, j.intensity_out, p.H, p.twx, p.twy,
                               j.nx, j.ny, j.steps,
-                              (float)(2.0 * 3.14159265358979323846 / j.wavelength * j.dz)};
+                              (float)(2.0 * 3.14159265358979323846 / j.wavelength * j.dz),
+                              j.clear_steps};
     }
     // segment table: round r holds pass r of every job that has it, jobs of
     // equal pass size side by side
@@ -459,7 +464,7 @@ int bpm_propagate_batch(const bpm_job* jobs, int n_jobs, void* workspace,
         bpm::MarchIO io[bpm::kMaxFields];
         for (int i = 0; i < n_jobs; ++i)
             io[i] = bpm::MarchIO{jobs[i].field_in, jobs[i].dn, jobs[i].field_out,
-                                 jobs[i].intensity_out};
+                                 jobs[i].intensity_out, jobs[i].clear_steps};
         return device_status(bpm::launch_forward(g, p, io, n_jobs, s, nullptr, var),
                              "batch march");
     }
@@ -498,7 +503,8 @@ int bpm_march_phase_times(const bpm_job* jobs, int n_jobs, void* workspace,
     if ((rc = device_status(hipMemsetAsync(timers, 0, timer_bytes, s), "timers"))) return rc;
     bpm::MarchIO io[bpm::kMaxFields];
     for (int i = 0; i < n_jobs; ++i)
-        io[i] = bpm::MarchIO{jobs[i].field_in, jobs[i].dn, jobs[i].field_out, jobs[i].intensity_out};
+        io[i] = bpm::MarchIO{jobs[i].field_in, jobs[i].dn, jobs[i].field_out, jobs[i].intensity_out,
+                             jobs[i].clear_steps};
     return device_status(bpm::launch_forward(g, p, io, n_jobs, s, timers, var), "timed march");
 }
 

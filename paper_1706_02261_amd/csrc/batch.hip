@@ -51,8 +51,8 @@ template <int NX>
 __device__ __attribute__((noinline)) void batch_row(const g_float2* field_in, g_float2* work_g,
                                                     const g_float* dn, g_float* inten,
                                                     const g_float2* twx, int nx, int ny,
-                                                    int steps, float k0dz, int pass, int item,
-                                                    lds_float2* lds) {
+                                                    int steps, float k0dz, int clear, int pass,
+                                                    int item, lds_float2* lds) {
     float2* smem = (float2*)lds;
     float2* work = (float2*)work_g;
     OpaqueTwiddles<NX, kR> tw;
@@ -80,10 +80,16 @@ __device__ __attribute__((noinline)) void batch_row(const g_float2* field_in, g_
         const RowArgs ra{work, work, inten ? (float*)inten + s * plane : nullptr, nullptr,
                          nullptr, nullptr, nullptr, k0dz};
         row_load<NX, kSpecIn>(u0, ny, ra.src, va);
-        load_dn<NX>(d0, u0, ny, dns);
+        if (s >= clear)
+            load_dn<NX>(d0, u0, ny, dns);
+        else
+            zero_dn(d0);
         if (two) {
             row_load<NX, kSpecIn>(u1, ny, ra.src, vb);
-            load_dn<NX>(d1, u1, ny, dns);
+            if (s >= clear)
+                load_dn<NX>(d1, u1, ny, dns);
+            else
+                zero_dn(d1);
         }
         if (s + 1 < steps) {
             row_body<NX, kSpecIn, kScreen, kSpecOut>(u0, ny, ra, d0, tw, smem, va);
@@ -162,25 +168,25 @@ __global__ __launch_bounds__(kBlock) void batch_kernel(const BatchJob* __restric
             switch (jb.nx) {
                 case 32: batch_row<32>((const g_float2*)jb.field_in, (g_float2*)jb.work, (const g_float*)jb.dn,
                                                   (g_float*)jb.inten, (const g_float2*)jb.twx, jb.nx,
-                                                  jb.ny, jb.steps, jb.k0dz, sg.pass, tile, lds); break;
+                                                  jb.ny, jb.steps, jb.k0dz, jb.clear, sg.pass, tile, lds); break;
                 case 64: batch_row<64>((const g_float2*)jb.field_in, (g_float2*)jb.work, (const g_float*)jb.dn,
                                                   (g_float*)jb.inten, (const g_float2*)jb.twx, jb.nx,
-                                                  jb.ny, jb.steps, jb.k0dz, sg.pass, tile, lds); break;
+                                                  jb.ny, jb.steps, jb.k0dz, jb.clear, sg.pass, tile, lds); break;
                 case 128: batch_row<128>((const g_float2*)jb.field_in, (g_float2*)jb.work, (const g_float*)jb.dn,
                                                   (g_float*)jb.inten, (const g_float2*)jb.twx, jb.nx,
-                                                  jb.ny, jb.steps, jb.k0dz, sg.pass, tile, lds); break;
+                                                  jb.ny, jb.steps, jb.k0dz, jb.clear, sg.pass, tile, lds); break;
                 case 256: batch_row<256>((const g_float2*)jb.field_in, (g_float2*)jb.work, (const g_float*)jb.dn,
                                                   (g_float*)jb.inten, (const g_float2*)jb.twx, jb.nx,
-                                                  jb.ny, jb.steps, jb.k0dz, sg.pass, tile, lds); break;
+                                                  jb.ny, jb.steps, jb.k0dz, jb.clear, sg.pass, tile, lds); break;
                 case 512: batch_row<512>((const g_float2*)jb.field_in, (g_float2*)jb.work, (const g_float*)jb.dn,
                                                   (g_float*)jb.inten, (const g_float2*)jb.twx, jb.nx,
-                                                  jb.ny, jb.steps, jb.k0dz, sg.pass, tile, lds); break;
+                                                  jb.ny, jb.steps, jb.k0dz, jb.clear, sg.pass, tile, lds); break;
                 case 1024: batch_row<1024>((const g_float2*)jb.field_in, (g_float2*)jb.work, (const g_float*)jb.dn,
                                                   (g_float*)jb.inten, (const g_float2*)jb.twx, jb.nx,
-                                                  jb.ny, jb.steps, jb.k0dz, sg.pass, tile, lds); break;
+                                                  jb.ny, jb.steps, jb.k0dz, jb.clear, sg.pass, tile, lds); break;
                 case 2048: batch_row<2048>((const g_float2*)jb.field_in, (g_float2*)jb.work, (const g_float*)jb.dn,
                                                   (g_float*)jb.inten, (const g_float2*)jb.twx, jb.nx,
-                                                  jb.ny, jb.steps, jb.k0dz, sg.pass, tile, lds); break;
+                                                  jb.ny, jb.steps, jb.k0dz, jb.clear, sg.pass, tile, lds); break;
                 default: break;
             }
         } else {

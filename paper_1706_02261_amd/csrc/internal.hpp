@@ -71,6 +71,7 @@ struct MarchIO {
     const float* dn;       // [steps][ny][nx]
     void* field_out;       // float2 [ny][nx]
     float* intensity;      // [steps][ny][nx] or nullptr
+    int clear;             // leading steps without a screen (dn not read)
 };
 // timers: per-workgroup phase timers (diagnostic, see PhaseTimers) or null
 // variant: the kernel (MarchVariant), kMarchAuto to resolve it here; a caller
@@ -121,6 +122,7 @@ struct BatchJob {
     const void* twy;
     int nx, ny, steps;
     float k0dz;
+    int clear;  // leading steps without a screen
 };
 struct BatchSeg {
     int job, pass, first, count, need;

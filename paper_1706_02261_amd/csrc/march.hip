@@ -379,6 +379,7 @@ hipError_t launch_forward(const Geom& g, const Plan& p, const MarchIO* io, int f
         a.work[f] = (float2*)io[f].field_out;
         a.dn[f] = io[f].dn;
         a.inten[f] = io[f].intensity;
+        a.clear[f] = io[f].clear;
     }
     a.H = (const float2*)p.H;
     a.twx = (const float2*)p.twx;

@@ -50,6 +50,7 @@ struct MarchArgs {
     int nx, ny, steps, fields;
     int variant;  // kernel of the march (MarchVariant), resolved on the host
     float k0dz;
+    int clear[kMaxFields];  // leading steps of each field without a screen
 };
 
 // OCC = workgroups per CU.  OCC 1 keeps the twiddles in registers and walks
@@ -107,7 +108,12 @@ __global__ __launch_bounds__(BLK, OCC) void march_kernel(MarchArgs a) {
     const bool one_row_unit = all_r <= G;
     const int vv = v < all_r ? v : 0;
     for (int j = 0; j < a.steps; ++j) {
-        if (one_row_unit) load_dn<NX, BLK>(d, vv / F, a.ny, a.dn[vv % F] + j * plane);
+        if (one_row_unit) {
+            if (j >= a.clear[vv % F])
+                load_dn<NX, BLK>(d, vv / F, a.ny, a.dn[vv % F] + j * plane);
+            else
+                zero_dn(d);
+        }
         tm.mark(kPhRow);
         grid_sync(a.counter, ++nbar, abort, a.status, a.limit, tm);
         for (int u = v; u < all_c; u += PAIR * G) {
@@ -133,10 +139,18 @@ __global__ __launch_bounds__(BLK, OCC) void march_kernel(MarchArgs a) {
             float2 va[kR], vb[kR];
             float db[kR];
             row_load<NX, kSpecIn, BLK>(r1, a.ny, a.work[f1], va);
-            if (!one_row_unit) load_dn<NX, BLK>(d, r1, a.ny, a.dn[f1] + j * plane);
+            if (!one_row_unit) {
+                if (j >= a.clear[f1])
+                    load_dn<NX, BLK>(d, r1, a.ny, a.dn[f1] + j * plane);
+                else
+                    zero_dn(d);
+            }
             if (two) {
                 row_load<NX, kSpecIn, BLK>(r2, a.ny, a.work[f2], vb);
-                load_dn<NX, BLK>(db, r2, a.ny, a.dn[f2] + j * plane);
+                if (j >= a.clear[f2])
+                    load_dn<NX, BLK>(db, r2, a.ny, a.dn[f2] + j * plane);
+                else
+                    zero_dn(db);
             }
             const RowArgs ra{a.work[f1], a.work[f1],
                              a.inten[f1] ? a.inten[f1] + j * plane : nullptr, nullptr, nullptr,
@@ -229,7 +243,10 @@ __global__ __launch_bounds__(kBlock, 2) void march_duo_kernel(MarchArgs a) {
         asm volatile("" : "+s"(u));
         float2 vals[kR], h[kR];
         arrive();
-        trow_dn<NX, NY>(u, a.dn[f] + (size_t)j * plane, d);
+        if (j >= a.clear[f])
+            trow_dn<NX, NY>(u, a.dn[f] + (size_t)j * plane, d);
+        else
+            zero_dn(d);
         tcol_h<NX, NY>(u, a.H, h);
         wait();
         tcol_load<NX, NY>(u, a.work[f], vals);

@@ -94,6 +94,12 @@ __device__ __forceinline__ void apply_screen(float2 (&v)[kR], const float (&ph)[
 }
 
 // dn of this thread's row unit, fetched ahead of the row pass
+// dn of a step without a screen (the background medium)
+__device__ __forceinline__ void zero_dn(float (&d)[kR]) {
+#pragma unroll
+    for (int i = 0; i < kR; ++i) d[i] = 0.f;
+}
+
 template <int NX, int BLK = kBlock>
 __device__ __forceinline__ void load_dn(float (&d)[kR], int unit, int ny,
                                         const float* __restrict__ dn) {

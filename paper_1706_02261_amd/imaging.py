@@ -3,9 +3,9 @@ light-sheet simulation).
 
 The detection objective is focused on slice ``focal_slice`` of a dn volume.
 For every depth z of a slab around it, point sources on a pitch grid at
-depth z ride in one multiplexed field, march to the exit plane (all depths in
-one uneven batch launch) and are brought back through the detection pupil to
-the focal plane (``bpm_psf_readout`` with one plane, back_steps = nz -
+depth z ride in one multiplexed field, march to the exit plane (the depths in
+lockstep launches of equal-length jobs, see ``focal_plane_psfs``) and are
+brought back through the detection pupil to the focal plane (``bpm_psf_readout`` with one plane, back_steps = nz -
 focal_slice); their crops are the node PSFs of that depth in the camera
 plane.  ``bpm_camera_accumulate`` then adds the depth's emission
 (excitation x fluorophore density) through the node PSFs, blended
@@ -54,20 +54,27 @@ def camera_accumulate(image: torch.Tensor, excitation: torch.Tensor, node_psfs: 
 def focal_plane_psfs(dn: torch.Tensor, depths, focal_slice: int, pitch: int,
                      optics: Optics = Optics(), crop: int = 32, scale: float = 1.0):
     """Node PSFs [len(depths)][gy][gx][crop][crop] in the focal plane of
-    sources at each depth (one uneven batch march, one readout per depth)."""
+    sources at each depth, one readout per depth.  All depths march from the
+    shallowest one, z0: the sources of depth z enter as the clear-medium
+    field that focuses (z - z0) dz downstream and skip the screens of slices
+    z0 .. z - 1 (``clear_steps``), which leaves the volume exactly as a march
+    from z; the jobs then have one length and march in lockstep."""
     _need(dn, "dn", torch.float32)
     nz, ny, nx = dn.shape
     if not 0 <= focal_slice <= nz:
         raise ValueError(f"focal_slice={focal_slice} must be in [0, {nz}]")
     src = node_sources(ny, nx, pitch, dn.device)
-    jobs = []
     for z in depths:
         if not 0 <= z < nz:
             raise ValueError(f"depth {z} outside [0, {nz})")
+    z0 = min(depths)
+    jobs = []
+    for z in depths:
         u0 = _bpm.point_sources(src, nx, ny, optics.dx, optics.wavelength, optics.n0, optics.na,
-                                0.0)
-        jobs.append(dict(field=u0, dn=dn[z:], dx=optics.dx, dz=optics.dz,
-                         wavelength=optics.wavelength, n0=optics.n0, out=u0, intensity=False))
+                                (z - z0) * optics.dz)
+        jobs.append(dict(field=u0, dn=dn[z0:], dx=optics.dx, dz=optics.dz,
+                         wavelength=optics.wavelength, n0=optics.n0, out=u0, intensity=False,
+                         clear_steps=z - z0))
     exits = _bpm.propagate_batch(jobs)
     gy, gx = ny // pitch, nx // pitch
     out = torch.empty((len(jobs), gy, gx, crop, crop), dtype=torch.float32, device=dn.device)

@@ -136,6 +136,11 @@ def test_batch_validation(L):
     assert L.bpm_propagate_batch(jobs, 0, b.p, 1 << 30, None) == B.BPM_ERR_INVALID_ARG
     jobs[1] = B.Job(b.p, None, 64, 64, 3, 0.2, 0.2, 0.5, 1.33, b.p, 0)
     assert L.bpm_propagate_batch(jobs, 2, b.p, 1 << 30, None) == B.BPM_ERR_INVALID_ARG
+    jobs[1] = B.Job(b.p, b.p, 64, 64, 3, 0.2, 0.2, 0.5, 1.33, b.p, 0, 4)     # clear_steps > steps
+    assert L.bpm_propagate_batch(jobs, 2, b.p, 1 << 30, None) == B.BPM_ERR_INVALID_ARG
+    assert b"clear_steps" in L.bpm_last_error()
+    jobs[1] = B.Job(b.p, b.p, 64, 64, 3, 0.2, 0.2, 0.5, 1.33, b.p, 0, -1)
+    assert L.bpm_propagate_batch(jobs, 2, b.p, 1 << 30, None) == B.BPM_ERR_INVALID_ARG
     jobs[1] = B.Job(b.p, b.p, 64, 64, 3, 0.2, 0.2, 0.5, 1.33, b.p, 0)
     need = L.bpm_batch_workspace_size(jobs, 2)
     assert need > 2 * L.bpm_workspace_size(64, 64, 3, 0)

@@ -190,3 +190,63 @@ def test_captured_graph_of_the_64_job_mix():
         for k, (o, i) in enumerate(prep.results):
             assert np.array_equal(o.cpu().numpy(), ref[k][0]), (rep, k)
             assert np.array_equal(i.cpu().numpy(), ref[k][1]), (rep, k)
+
+
+# ---------------------------------------------------------------------------
+# staggered starts (clear_steps)
+
+def _clear_case(nx, ny, steps, k, seed):
+    rng = np.random.default_rng(seed)
+    u = (rng.standard_normal((ny, nx)) + 1j * rng.standard_normal((ny, nx))).astype(np.complex64)
+    dn = rng.uniform(0, 0.05, (steps, ny, nx)).astype(np.float32)
+    zeroed = dn.copy()
+    zeroed[:k] = 0.0
+    return u, dn, zeroed
+
+
+@pytest.mark.parametrize("shape", [(256, 256, 9, 2), (1024, 1024, 6, 2), (128, 64, 7, 3),
+                                   (512, 512, 5, 1)])
+def test_clear_steps_equal_a_zeroed_prefix(shape):
+    """Jobs whose first k screens are skipped give the bits of jobs whose
+    first k dn slices are zero, in the lockstep kernels and the work queue."""
+    import paper_1706_02261_amd as bpm
+    nx, ny, steps, fields = shape
+    ks = [3, 0, steps][:fields]
+    cases = [_clear_case(nx, ny, steps, k, seed=nx + 7 * k) for k in ks]
+    def jobs(clear):
+        out = []
+        for (u, dn, zeroed), k in zip(cases, ks):
+            out.append(dict(field=torch.from_numpy(u).cuda(),
+                            dn=torch.from_numpy(dn if clear else zeroed).cuda(), dx=0.2, dz=0.2,
+                            wavelength=0.5, n0=1.33, clear_steps=k if clear else 0))
+        return out
+    a = bpm.propagate_batch(jobs(True))
+    b = bpm.propagate_batch(jobs(False))
+    # the work queue: an extra job of another size forces the uneven path
+    extra = dict(field=torch.zeros((32, 32), dtype=torch.complex64, device="cuda"),
+                 dn=torch.zeros((2, 32, 32), device="cuda"), dx=0.2, dz=0.2, wavelength=0.5,
+                 n0=1.33)
+    c = bpm.propagate_batch(jobs(True) + [extra])[:len(ks)]
+    torch.cuda.synchronize()
+    for (oa, ia), (ob, ib), (oc, ic) in zip(a, b, c):
+        assert torch.equal(oa, ob) and torch.equal(ia, ib)
+        assert torch.equal(oc, ob) and torch.equal(ic, ib)
+
+
+def test_staggered_start_matches_the_march_from_depth():
+    """A source entered k slices early, defocused by k dz, with k cleared
+    steps, leaves the volume as the oracle's in-focus source marched from
+    slice k."""
+    import paper_1706_02261_amd as bpm
+    n, steps, k = 256, 20, 7
+    rng = np.random.default_rng(12)
+    dn = rng.uniform(0, 0.04, (steps, n, n)).astype(np.float32)
+    src = np.array([[40, 50], [200, 130]], np.int32)
+    u_early = bpm.point_sources(torch.from_numpy(src).cuda(), n, n, 0.2, 0.5, 1.33, 0.6, k * 0.2)
+    (out, _), = bpm.propagate_batch([dict(field=u_early, dn=torch.from_numpy(dn).cuda(), dx=0.2,
+                                          dz=0.2, wavelength=0.5, n0=1.33, clear_steps=k,
+                                          intensity=False)])
+    u0 = oracle.point_sources(n, n, 0.2, 0.5, 1.33, 0.6, 0.0, src)
+    ref, _ = oracle.bpm_forward(u0, dn[k:], 0.2, 0.2, 0.5, 1.33, intensity=False)
+    got = out.cpu().numpy()
+    assert np.linalg.norm(got - ref) / np.linalg.norm(ref) <= 2e-5
