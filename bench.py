@@ -490,7 +490,7 @@ def ao_rates(dev, reps=5):
     corr, unc, clear = at(phi, dn_t), at(aim, dn_t), at(aim, torch.zeros_like(dn_t))
     best = ao.optimum_intensity(amp_t, gs)
     ms_gs = timed(lambda: ao.guide_star_phase(dn_t, f, zf, opt))
-    prob = ao._FocusProblem(dn_t, [f])
+    prob = ao.FocusProblem(dn_t, [f])
     ms_it = timed(lambda: prob.gradient(amp_t, aim, dn_t, zf, opt))
     shifts = [(0, s) for s in range(1, 7)] + [(s, 0) for s in range(1, 7)]
     ms_me = timed(lambda: ao.memory_effect(amp_t, gs, dn_t, f, shifts, zf, opt))

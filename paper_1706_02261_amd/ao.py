@@ -87,8 +87,9 @@ def optimum_intensity(amplitude: torch.Tensor, gs: torch.Tensor) -> float:
     return float((amplitude.double() * gs.abs().double()).sum()) ** 2
 
 
-class _FocusProblem:
-    """Buffers of the multi-focus objective L = -sum_f |u(x_f)|^2."""
+class FocusProblem:
+    """The multi-focus objective L = -sum_f |u(x_f)|^2 on one tissue, with its
+    buffers (workspace, adjoint source) kept across calls of ``gradient``."""
 
     def __init__(self, dn, foci):
         _, ny, nx = dn.shape
@@ -123,7 +124,7 @@ def focus_gradient(amplitude: torch.Tensor, phase: torch.Tensor, dn: torch.Tenso
     _need(amplitude, "amplitude", torch.float32)
     _need(phase, "phase", torch.float32)
     _need(dn, "dn", torch.float32)
-    return _FocusProblem(dn, foci).gradient(amplitude, phase, dn, z_focus, optics)
+    return FocusProblem(dn, foci).gradient(amplitude, phase, dn, z_focus, optics)
 
 
 def optimize_pupil(amplitude: torch.Tensor, dn: torch.Tensor, foci, z_focus: float,
@@ -140,7 +141,7 @@ def optimize_pupil(amplitude: torch.Tensor, dn: torch.Tensor, foci, z_focus: flo
              else phase0.clone().contiguous())
     m = torch.zeros_like(phase)
     v = torch.zeros_like(phase)
-    prob = _FocusProblem(dn, foci)
+    prob = FocusProblem(dn, foci)
     hist = torch.empty((iters, len(foci)), dtype=torch.float32, device=dev)
     for t in range(1, iters + 1):
         hist[t - 1], gphi = prob.gradient(amplitude, phase, dn, z_focus, optics)
