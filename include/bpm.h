@@ -412,10 +412,11 @@ int psf_surrogate_infer(const void* weights_bf16, size_t weights_bytes,
  *   BPM_MARCH_ONE_PER_CU   one 256-thread workgroup per CU, twiddles in
  *                          registers, a workgroup's units two at a time;
  *   BPM_MARCH_TWO_PER_CU   two workgroups per CU, twiddles in LDS (nx, ny >= 512);
- *   BPM_MARCH_TILED_PAIR   two fields with a grid barrier each, two workgroups
- *                          per CU holding different fields, the field kept in
- *                          128-byte tiles between passes (two fields with
- *                          nx ny = 2^20 on a device of 256 CUs);
+ *   BPM_MARCH_TILED_PAIR   one or two fields with a grid barrier each, one
+ *                          workgroup per CU and field (two fields: the two
+ *                          workgroups of a CU hold different fields), the
+ *                          field kept in 128-byte tiles between passes (one or
+ *                          two fields with nx ny = 2^20 on a device of 256 CUs);
  *   BPM_MARCH_SMALL_BLOCKS 64-thread workgroups, up to four per CU, twiddles in
  *                          registers (nx, ny <= 1024): four times as many
  *                          units per pass, for fields too small to give

@@ -163,9 +163,12 @@ int bpm_propagate(const bpm_c64* field_in, const float* dn, int nx, int ny, int 
     hipStream_t s = static_cast<hipStream_t>(hip_stream);
     const bpm::Geom g{nx, ny, steps, dx, dz, wavelength, n0};
     const bpm::Plan p = bpm::plan_carve(workspace, nx, ny);
-    if ((rc = device_status(bpm::launch_plan(g, p, true, s), "plan"))) return rc;
+    const int var = bpm::march_variant(nx, ny, 1);
+    if ((rc = device_status(bpm::launch_plan(g, p, true, s, var == bpm::kMarchTiledPair),
+                            "plan")))
+        return rc;
     const bpm::MarchIO io{field_in, dn, field_out, intensity_out};
-    return device_status(bpm::launch_forward(g, p, &io, 1, s), "forward march");
+    return device_status(bpm::launch_forward(g, p, &io, 1, s, nullptr, var), "forward march");
 }
 
 int bpm_slice_means(const float* dn, int nx, int ny, int steps, float* dn_ref, void* hip_stream) {

@@ -12,7 +12,7 @@ inline size_t align_up(size_t v) { return (v + kAlign - 1) / kAlign * kAlign; }
 
 // Kernels of the forward march (values of bpm.h's BPM_MARCH_*): one
 // workgroup per CU with register twiddles; two per CU with LDS twiddles; the
-// two-field tiled march.  march_variant gives the one a march of `fields`
+// tiled march of one or two fields.  march_variant gives the one a march of `fields`
 // lockstep fields of this geometry takes: the override set for the shape
 // (bpm_set_march_variant, e.g. from the launch-shape tuner) when eligible,
 // else the built-in choice.
@@ -21,7 +21,7 @@ enum MarchVariant : int { kMarchAuto = 0, kMarchOnePerCu = 1, kMarchTwoPerCu = 2
 bool march_variant_eligible(int nx, int ny, int fields, int variant);
 int march_variant(int nx, int ny, int fields);
 int set_march_variant(int nx, int ny, int fields, int variant);  // 0 ok, -1 ineligible
-// whether such a march takes the two-field tiled kernel (and so needs a tiled
+// whether such a march takes the tiled kernel (and so needs a tiled
 // propagator table)
 bool march_tiled(int nx, int ny, int fields);
 

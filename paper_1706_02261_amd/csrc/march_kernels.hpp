@@ -177,12 +177,13 @@ __global__ __launch_bounds__(BLK, OCC) void march_kernel(MarchArgs a) {
 }
 
 // ---------------------------------------------------------------------------
-// two-field march: a barrier per field, tiled field layout
+// tiled march (one or two fields): a barrier per field, tiled field layout
 //
-// For two fields whose passes have one unit per CU each (nx ny = 2^20).  Two
-// workgroups per CU; every workgroup works on one field only, one unit of
-// each of its field's passes, and each field has a grid barrier of its own.
-// Workgroups are laid out so that the two that share a CU (dealt 256 apart:
+// For NF = 1 or 2 fields whose passes have one unit per CU each
+// (nx ny = 2^20).  NF workgroups per CU; every workgroup works on one field
+// only, one unit of each of its field's passes, and each field has a grid
+// barrier of its own.
+// With two fields, workgroups are laid out so that the two that share a CU (dealt 256 apart:
 // virtual ids 32 apart within one XCD's range) belong to different fields,
 // while an XCD's workgroups of both fields hold the same 32-unit range (one
 // slice of the propagator table in its L2).  When one field's workgroups wait
@@ -191,18 +192,18 @@ __global__ __launch_bounds__(BLK, OCC) void march_kernel(MarchArgs a) {
 // (in field_out; the head and tail passes convert in place), and the plan
 // stores the propagator table in the same layout.
 
-template <int NX, int NY>
-__global__ __launch_bounds__(kBlock, 2) void march_duo_kernel(MarchArgs a) {
+template <int NX, int NY, int NF>
+__global__ __launch_bounds__(kBlock, NF) void march_duo_kernel(MarchArgs a) {
     extern __shared__ float2 smem[];
     PhaseTimers tm;
     tm.start(a.timers);
     const int G = gridDim.x, v = virtual_block();
-    const int Gx = G / 8, half = Gx / 2;            // workgroups per XCD, per field and XCD
+    const int Gx = G / 8, half = Gx / NF;           // workgroups per XCD, per field and XCD
     const int f = (v % Gx) / half;                  // this workgroup's field
     const int unit = (v / Gx) * half + v % half;    // its unit of every pass of that field
     const size_t plane = (size_t)NX * NY;
     unsigned* bar = a.counter + f * kFieldBarWords;
-    const unsigned GF = (unsigned)(G / 2);
+    const unsigned GF = (unsigned)(G / NF);
     bool abort = false;
     float2* tabx = smem + march_data_lds<NX, NY>() / sizeof(float2);
     float2* taby = tabx + LdsTwiddleTable<NX, kR>::size();
@@ -584,9 +585,14 @@ hipError_t launch_forward_x(const MarchArgs& a, hipStream_t s) {
         void* args[] = {const_cast<MarchArgs*>(&a)};
         const int cus = device_cus();
         if constexpr (units_per_block<NX>() * units_per_block<NY>() == 16) {
-            if (a.variant == kMarchTiledPair)
+            if (a.variant == kMarchTiledPair && a.fields == 2)
                 return hipLaunchCooperativeKernel(
-                    reinterpret_cast<const void*>(&march_duo_kernel<NX, NY>), dim3(2 * cus),
+                    reinterpret_cast<const void*>(&march_duo_kernel<NX, NY, 2>), dim3(2 * cus),
+                    dim3(kBlock), args,
+                    (unsigned)(march_data_lds<NX, NY>() + march_twiddle_lds<NX, NY>()), s);
+            if (a.variant == kMarchTiledPair && a.fields == 1)
+                return hipLaunchCooperativeKernel(
+                    reinterpret_cast<const void*>(&march_duo_kernel<NX, NY, 1>), dim3(cus),
                     dim3(kBlock), args,
                     (unsigned)(march_data_lds<NX, NY>() + march_twiddle_lds<NX, NY>()), s);
         }

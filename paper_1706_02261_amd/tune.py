@@ -2,7 +2,7 @@
 
 For each shape (nx, ny, lockstep fields) the library offers one or more
 kernels (include/bpm.h, BPM_MARCH_*): one workgroup per CU with register
-twiddles, two per CU with LDS twiddles, the two-field tiled march, and
+twiddles, two per CU with LDS twiddles, the tiled march of one or two fields, and
 64-thread workgroups for small fields.  They
 give identical results; which is fastest depends on the shape and the device.
 ``tune`` times every eligible kernel of each shape on the current device (a
