@@ -53,9 +53,11 @@ def test_plain_workload_parity():
 
 
 @pytest.mark.parametrize("nx,ny", [(32, 32), (64, 32), (32, 2048), (2048, 32), (128, 256),
-                                   (512, 64), (256, 1024), (2048, 128)])
+                                   (512, 64), (256, 1024), (2048, 128), (1024, 1024),
+                                   (2048, 512), (512, 2048)])
 def test_sizes_parity(nx, ny):
-    """Every supported size class (non-square both ways), 3 steps, random field."""
+    """Every supported size class (non-square both ways), 3 steps, random field;
+    fields of 2^20 points take the tiled kernel."""
     g, u0, dn = random_case(nx, ny, 3, seed=nx * 7 + ny)
     u, inten = gpu_march(u0, dn, g)
     ru, ri = ora_march(u0, dn, g)
