@@ -348,12 +348,50 @@ def adjoint_rate(dev, reps=3):
     ms = float(np.median(ts))
     vs = g.nx * g.ny * g.steps
     achieved = ADJOINT_BYTES_PER_VOXEL_STEP * vs / (ms / 1e3) / 1e9
+
+    # eight guide stars (foci at eight lateral positions of the exit plane)
+    # through the same tissue, one lockstep bpm_adjoint_batch launch
+    n_stars = 8
+    gIs = []
+    for k in range(n_stars):
+        t = torch.zeros_like(gI)
+        t[-1, g.ny // 2 + 8 * (k // 4) - 4, g.nx // 2 + 8 * (k % 4) - 12] = -1.0
+        gIs.append(t)
+    jobs = [dict(field=u0, dn=dn, grad_intensity=t, want_field=False, want_spectrum=True,
+                 want_dn=True) for t in gIs]
+    ws = bpm.workspace(bpm.bpm.adjoint_batch_workspace_size(n_stars, g.nx, g.ny, g.steps), dev)
+
+    def run_batch():
+        return bpm.adjoint_batch(jobs, g.dx, g.dz, g.wavelength, g.n0, ws=ws, stream=stream)
+
+    run_batch()
+    torch.cuda.synchronize(dev)
+    tb = []
+    for _ in range(reps):
+        a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        a.record(stream)
+        run_batch()
+        b.record(stream)
+        torch.cuda.synchronize(dev)
+        tb.append(a.elapsed_time(b))
+    msb = float(np.median(tb))
+    achieved_b = ADJOINT_BYTES_PER_VOXEL_STEP * n_stars * vs / (msb / 1e3) / 1e9
+    del ws, jobs, gIs
     return {"workload": f"adjoint {g.nx}x{g.ny}x{g.steps}, sqrt(N) checkpoints, gradients "
                         "w.r.t. pupil spectrum and dn",
             "ms": round(ms, 3), "gvoxel_steps_per_s": round(vs / (ms / 1e3) / 1e9, 3),
             "roofline": {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,
                          "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),
-                         "bytes_per_voxel_step": ADJOINT_BYTES_PER_VOXEL_STEP}}
+                         "bytes_per_voxel_step": ADJOINT_BYTES_PER_VOXEL_STEP},
+            "lockstep": {"workload": f"{n_stars} guide stars of the same workload in one "
+                                     "bpm_adjoint_batch launch",
+                         "ms": round(msb, 3),
+                         "gvoxel_steps_per_s": round(n_stars * vs / (msb / 1e3) / 1e9, 3),
+                         "speedup_vs_separate_calls": round(n_stars * ms / msb, 2),
+                         "roofline": {"bound": "hbm", "achieved": round(achieved_b, 1),
+                                      "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                                      "frac": round(achieved_b / HBM_PEAK_GBS, 4),
+                                      "bytes_per_voxel_step": ADJOINT_BYTES_PER_VOXEL_STEP}}}
 
 
 def batch_rate(dev, replays=3):

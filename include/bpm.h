@@ -227,6 +227,37 @@ int bpm_adjoint(const bpm_c64* field_in, const float* dn, int nx, int ny, int st
                 int checkpoint_every, void* workspace, size_t workspace_bytes,
                 void* hip_stream);
 
+/* Several adjoints of one geometry (the same nx, ny, steps, dx, dz,
+ * wavelength, n0 and checkpoint interval) in one lockstep launch: every pass
+ * covers the units of all fields, so the fields share each grid barrier
+ * (throughput for several guide stars or losses; one adjoint is latency
+ * bound).  One job per field, each with the pointers of bpm_adjoint and the
+ * same meaning and NULL rules; the jobs' outputs must not overlap each other
+ * or any input.  Results are bitwise those of separate bpm_adjoint calls.
+ * When no job gives grad_intensity or grad_dn the launch takes the linear
+ * path of bpm_adjoint; otherwise it runs the forward march of every job that
+ * gives field_in (a job without one must be linear, as in bpm_adjoint).
+ *   n_fields  1 .. BPM_MAX_LOCKSTEP_FIELDS, else BPM_ERR_INVALID_ARG.
+ *   workspace bpm_adjoint_batch_workspace_size(n_fields, ...) bytes,
+ *             256-byte aligned: the plan and each field's checkpoints. */
+#define BPM_MAX_LOCKSTEP_FIELDS 8
+typedef struct bpm_adjoint_job {
+    const bpm_c64* field_in;
+    const float* dn;
+    const bpm_c64* grad_field_out;
+    const float* grad_intensity;
+    bpm_c64* grad_field_in;
+    bpm_c64* grad_spectrum_in;
+    float* grad_dn;
+} bpm_adjoint_job;
+/* 0 for n_fields outside 1 .. BPM_MAX_LOCKSTEP_FIELDS or arguments that
+ * bpm_adjoint_workspace_size rejects. */
+size_t bpm_adjoint_batch_workspace_size(int n_fields, int nx, int ny, int steps,
+                                        int checkpoint_every);
+int bpm_adjoint_batch(const bpm_adjoint_job* jobs, int n_fields, int nx, int ny, int steps,
+                      double dx, double dz, double wavelength, double n0, int checkpoint_every,
+                      void* workspace, size_t workspace_bytes, void* hip_stream);
+
 /* Bytes of workspace for bpm_fft2. */
 size_t bpm_fft2_workspace_size(int nx, int ny);
 

@@ -6,6 +6,7 @@ torch tensors (device memory and streams) into the C ABI.
 """
 from ._lib import BpmError, lib  # noqa: F401
 from .bpm import (BPMFunction, PreparedBatch, PupilBPMFunction, adam_step, adjoint,  # noqa: F401
+                  adjoint_batch,
                   fft2, guide_star_phase, march_phase_times, point_sources, propagate, propagate_adapted,
                   propagate_batch, psf_readout, slice_means,
                   pupil_phase_grad, pupil_spectrum, set_wait_limit, workspace,
@@ -15,4 +16,4 @@ __all__ = ["BpmError", "lib", "propagate", "propagate_batch", "PreparedBatch", "
            "pupil_spectrum", "pupil_phase_grad", "psf_readout", "point_sources", "BPMFunction",
            "PupilBPMFunction", "workspace", "workspace_size", "workspace_status",
            "set_wait_limit", "march_phase_times", "propagate_adapted", "slice_means",
-           "guide_star_phase", "adam_step"]
+           "guide_star_phase", "adam_step", "adjoint_batch"]

@@ -27,6 +27,7 @@ EXPORTS = (
     "bpm_workspace_size", "bpm_propagate", "bpm_batch_workspace_size",
     "bpm_propagate_batch", "bpm_batch_upload", "bpm_batch_launch",
     "bpm_adjoint_workspace_size", "bpm_adjoint",
+    "bpm_adjoint_batch_workspace_size", "bpm_adjoint_batch",
     "psf_surrogate_infer", "bpm_error_string", "bpm_last_error",
     "bpm_fft2_workspace_size", "bpm_fft2", "bpm_pupil_spectrum", "bpm_pupil_phase_grad",
     "bpm_psf_readout_workspace_size", "bpm_psf_readout",
@@ -51,6 +52,7 @@ BPM_MARCH_TWO_PER_CU = 2
 BPM_MARCH_TILED_PAIR = 3
 BPM_MARCH_SMALL_BLOCKS = 4
 PHASE_TIMER_WORDS = 8 + 8 * 4096
+BPM_MAX_LOCKSTEP_FIELDS = 8
 
 
 class BpmError(RuntimeError):
@@ -67,6 +69,14 @@ class Job(ctypes.Structure):
                 ("wavelength", ctypes.c_double), ("n0", ctypes.c_double),
                 ("field_out", ctypes.c_void_p), ("intensity_out", ctypes.c_void_p),
                 ("clear_steps", ctypes.c_int)]
+
+
+class AdjointJob(ctypes.Structure):
+    """Mirror of ``bpm_adjoint_job``."""
+    _fields_ = [("field_in", ctypes.c_void_p), ("dn", ctypes.c_void_p),
+                ("grad_field_out", ctypes.c_void_p), ("grad_intensity", ctypes.c_void_p),
+                ("grad_field_in", ctypes.c_void_p), ("grad_spectrum_in", ctypes.c_void_p),
+                ("grad_dn", ctypes.c_void_p)]
 
 
 _lib = None
@@ -91,6 +101,11 @@ def _declare(L):
     L.bpm_adjoint.argtypes = [_V, _V, _I, _I, _I, _D, _D, _D, _D, _V, _V, _V, _V, _V, _I,
                               _V, _Z, _V]
     L.bpm_adjoint.restype = _I
+    L.bpm_adjoint_batch_workspace_size.argtypes = [_I, _I, _I, _I, _I]
+    L.bpm_adjoint_batch_workspace_size.restype = _Z
+    L.bpm_adjoint_batch.argtypes = [ctypes.POINTER(AdjointJob), _I, _I, _I, _I, _D, _D, _D, _D,
+                                    _I, _V, _Z, _V]
+    L.bpm_adjoint_batch.restype = _I
     L.psf_surrogate_infer.argtypes = [_V, _Z, _V, _V, _I, _V, _V, _V, _Z, _V]
     L.psf_surrogate_infer.restype = _I
     for name in ("psf_surrogate_param_count", "psf_surrogate_weights_bytes",

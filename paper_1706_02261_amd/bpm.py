@@ -206,6 +206,70 @@ def adjoint(field: torch.Tensor, dn: torch.Tensor, dx: float, dz: float, wavelen
     return g0, gs, gdn
 
 
+def adjoint_batch_workspace_size(n_fields: int, nx: int, ny: int, steps: int,
+                                 checkpoint_every: int = 0) -> int:
+    n = lib().bpm_adjoint_batch_workspace_size(n_fields, nx, ny, steps, checkpoint_every)
+    if n == 0:
+        raise _lib.BpmError(_lib.BPM_ERR_INVALID_ARG,
+                            f"no adjoint workspace for {n_fields} fields nx={nx} ny={ny} "
+                            f"steps={steps} checkpoint_every={checkpoint_every}")
+    return int(n)
+
+
+def adjoint_batch(jobs, dx: float, dz: float, wavelength: float, n0: float,
+                  checkpoint_every: int = 0, ws: torch.Tensor | None = None, stream=None):
+    """Several adjoints of one geometry in one lockstep launch (the fields
+    share each grid barrier); bitwise the results of separate ``adjoint``
+    calls.  Each job is a dict with ``dn`` and the optional ``field``,
+    ``grad_field_out``, ``grad_intensity``, ``want_field`` (default True),
+    ``want_spectrum`` (False) and ``want_dn`` (True) of ``adjoint``; at most
+    8 jobs.  Returns one ``(grad_field_in, grad_spectrum_in, grad_dn)`` per
+    job."""
+    if not 1 <= len(jobs) <= _lib.BPM_MAX_LOCKSTEP_FIELDS:
+        raise ValueError(f"{len(jobs)} jobs: 1 to {_lib.BPM_MAX_LOCKSTEP_FIELDS} per launch")
+    shape = None
+    table = (_lib.AdjointJob * len(jobs))()
+    outs = []
+    for k, j in enumerate(jobs):
+        dn = j["dn"]
+        _need(dn, "dn", torch.float32)
+        if dn.dim() != 3:
+            raise ValueError(f"job {k}: dn must be [steps][ny][nx]")
+        if shape is None:
+            shape = tuple(dn.shape)
+        elif tuple(dn.shape) != shape:
+            raise ValueError(f"job {k}: dn has shape {tuple(dn.shape)}, job 0 {shape}")
+        steps, ny, nx = shape
+        field, gout, gI = j.get("field"), j.get("grad_field_out"), j.get("grad_intensity")
+        want_dn = j.get("want_dn", True)
+        if field is None and (gout is None or gI is not None or want_dn):
+            raise ValueError(f"job {k}: field may be None only for the linear adjoint")
+        if field is not None:
+            _need(field, "field", torch.complex64, (ny, nx))
+        if gout is not None:
+            _need(gout, "grad_field_out", torch.complex64, (ny, nx))
+        if gI is not None:
+            _need(gI, "grad_intensity", torch.float32, (steps, ny, nx))
+        dev = dn.device
+        g0 = (torch.empty((ny, nx), dtype=torch.complex64, device=dev)
+              if j.get("want_field", True) else None)
+        gs = (torch.empty((ny, nx), dtype=torch.complex64, device=dev)
+              if j.get("want_spectrum", False) else None)
+        gdn = torch.empty((steps, ny, nx), dtype=torch.float32, device=dev) if want_dn else None
+        table[k] = _lib.AdjointJob(_ptr(field), _ptr(dn), _ptr(gout), _ptr(gI), _ptr(g0),
+                                   _ptr(gs), _ptr(gdn))
+        outs.append((g0, gs, gdn))
+    steps, ny, nx = shape
+    need = adjoint_batch_workspace_size(len(jobs), nx, ny, steps, checkpoint_every)
+    if ws is None:
+        ws = workspace(need, jobs[0]["dn"].device)
+    rc = lib().bpm_adjoint_batch(table, len(jobs), nx, ny, steps, float(dx), float(dz),
+                                 float(wavelength), float(n0), int(checkpoint_every), _ptr(ws),
+                                 ws.numel(), _stream_ptr(stream))
+    check(rc, "bpm_adjoint_batch")
+    return outs
+
+
 def fft2(x: torch.Tensor, inverse: bool = False, out: torch.Tensor | None = None, stream=None):
     """Natural-order 2-D DFT (numpy's fft2 / ifft2 conventions) of a complex64 [ny][nx]."""
     _need(x, "x", torch.complex64)

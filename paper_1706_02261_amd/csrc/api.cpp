@@ -543,34 +543,49 @@ static int checkpoint_interval(int steps, int checkpoint_every) {
 }
 
 size_t bpm_adjoint_workspace_size(int nx, int ny, int steps, int checkpoint_every) {
-    if (!pow2_in_range(nx) || !pow2_in_range(ny) || steps < 0 || checkpoint_every < 0) return 0;
-    if (steps > 0 && checkpoint_every > steps) return 0;
-    const size_t plane = sizeof(bpm_c64) * (size_t)nx * ny;
-    const size_t fields = steps > 0 ? bpm::adjoint_fields(steps, checkpoint_interval(steps, checkpoint_every)) : 0;
-    return bpm::plan_bytes(nx, ny) + bpm::align_up(plane * fields);
+    return bpm_adjoint_batch_workspace_size(1, nx, ny, steps, checkpoint_every);
 }
 
-int bpm_adjoint(const bpm_c64* field_in, const float* dn, int nx, int ny, int steps, double dx,
-                double dz, double wavelength, double n0, const bpm_c64* grad_field_out,
-                const float* grad_intensity, bpm_c64* grad_field_in, bpm_c64* grad_spectrum_in,
-                float* grad_dn, int checkpoint_every, void* workspace, size_t workspace_bytes,
-                void* hip_stream) {
+size_t bpm_adjoint_batch_workspace_size(int n_fields, int nx, int ny, int steps,
+                                        int checkpoint_every) {
+    if (n_fields < 1 || n_fields > BPM_MAX_LOCKSTEP_FIELDS) return 0;
+    if (!pow2_in_range(nx) || !pow2_in_range(ny) || steps < 0 || checkpoint_every < 0) return 0;
+    if (steps > 0 && checkpoint_every > steps) return 0;
+    const size_t per_field =
+        steps > 0 ? bpm::adjoint_field_bytes(nx, ny, steps, checkpoint_interval(steps, checkpoint_every))
+                  : 0;
+    return bpm::plan_bytes(nx, ny) + (size_t)n_fields * per_field;
+}
+
+// the adjoints of `n` jobs of one geometry, checked, in one lockstep launch
+static_assert(BPM_MAX_LOCKSTEP_FIELDS == bpm::kMaxFields, "lockstep field limit");
+
+static int adjoint_run(const bpm_adjoint_job* jobs, int n, int nx, int ny, int steps, double dx,
+                       double dz, double wavelength, double n0, int checkpoint_every,
+                       void* workspace, size_t workspace_bytes, void* hip_stream) {
     int rc = check_geom(nx, ny, steps, dx, dz, wavelength, n0);
     if (rc) return rc;
-    if (!field_in && (grad_intensity || grad_dn))
-        return fail(BPM_ERR_INVALID_ARG,
-                    "field_in must be non-null when grad_intensity or grad_dn is given");
-    if (steps > 0 && !dn) return fail(BPM_ERR_INVALID_ARG, "dn must be non-null when steps > 0");
     if (checkpoint_every < 0 || (steps > 0 && checkpoint_every > steps))
         return fail(BPM_ERR_INVALID_ARG, "checkpoint_every=%d must be 0 or in [1, steps=%d]",
                     checkpoint_every, steps);
-    const void* ptrs8[] = {field_in, grad_field_out, grad_field_in, grad_spectrum_in};
-    for (const void* q : ptrs8)
-        if (q && !aligned(q, 8)) return fail(BPM_ERR_INVALID_ARG, "complex arrays must be 8-byte aligned");
-    const void* ptrs4[] = {dn, grad_intensity, grad_dn};
-    for (const void* q : ptrs4)
-        if (q && !aligned(q, 4)) return fail(BPM_ERR_INVALID_ARG, "float arrays must be 4-byte aligned");
-    const size_t need = bpm_adjoint_workspace_size(nx, ny, steps, checkpoint_every);
+    for (int i = 0; i < n; ++i) {
+        const bpm_adjoint_job& j = jobs[i];
+        if (!j.field_in && (j.grad_intensity || j.grad_dn))
+            return fail(BPM_ERR_INVALID_ARG,
+                        "job %d: field_in must be non-null when grad_intensity or grad_dn is given",
+                        i);
+        if (steps > 0 && !j.dn)
+            return fail(BPM_ERR_INVALID_ARG, "job %d: dn must be non-null when steps > 0", i);
+        const void* ptrs8[] = {j.field_in, j.grad_field_out, j.grad_field_in, j.grad_spectrum_in};
+        for (const void* q : ptrs8)
+            if (q && !aligned(q, 8))
+                return fail(BPM_ERR_INVALID_ARG, "job %d: complex arrays must be 8-byte aligned", i);
+        const void* ptrs4[] = {j.dn, j.grad_intensity, j.grad_dn};
+        for (const void* q : ptrs4)
+            if (q && !aligned(q, 4))
+                return fail(BPM_ERR_INVALID_ARG, "job %d: float arrays must be 4-byte aligned", i);
+    }
+    const size_t need = bpm_adjoint_batch_workspace_size(n, nx, ny, steps, checkpoint_every);
     if ((rc = check_workspace(workspace, workspace_bytes, need))) return rc;
     hipStream_t s = static_cast<hipStream_t>(hip_stream);
     const bpm::Geom g{nx, ny, steps, dx, dz, wavelength, n0};
@@ -579,27 +594,56 @@ int bpm_adjoint(const bpm_c64* field_in, const float* dn, int nx, int ny, int st
     if (steps == 0) {
         // g_0 = dL/du_0 = dL/du_N; dL/dU_0 = DFT2(g_0) / (nx ny)
         if ((rc = device_status(bpm::launch_plan(g, p, false, s), "plan"))) return rc;
-        if (grad_field_in) {
-            hipError_t e = grad_field_out
-                ? hipMemcpyAsync(grad_field_in, grad_field_out, plane, hipMemcpyDeviceToDevice, s)
-                : hipMemsetAsync(grad_field_in, 0, plane, s);
-            if ((rc = device_status(e, "copy"))) return rc;
-        }
-        if (grad_spectrum_in) {
-            hipError_t e = grad_field_out
-                ? bpm::launch_fft2(grad_field_out, grad_spectrum_in, nx, ny, false,
-                                   (float)(1.0 / ((double)nx * ny)), p, s)
-                : hipMemsetAsync(grad_spectrum_in, 0, plane, s);
-            if ((rc = device_status(e, "spectrum"))) return rc;
+        for (int i = 0; i < n; ++i) {
+            const bpm_adjoint_job& j = jobs[i];
+            if (j.grad_field_in) {
+                hipError_t e = j.grad_field_out
+                    ? hipMemcpyAsync(j.grad_field_in, j.grad_field_out, plane,
+                                     hipMemcpyDeviceToDevice, s)
+                    : hipMemsetAsync(j.grad_field_in, 0, plane, s);
+                if ((rc = device_status(e, "copy"))) return rc;
+            }
+            if (j.grad_spectrum_in) {
+                hipError_t e = j.grad_field_out
+                    ? bpm::launch_fft2(j.grad_field_out, j.grad_spectrum_in, nx, ny, false,
+                                       (float)(1.0 / ((double)nx * ny)), p, s)
+                    : hipMemsetAsync(j.grad_spectrum_in, 0, plane, s);
+                if ((rc = device_status(e, "spectrum"))) return rc;
+            }
         }
         return BPM_OK;
     }
     if ((rc = device_status(bpm::launch_plan(g, p, true, s), "plan"))) return rc;
     const int K = checkpoint_interval(steps, checkpoint_every);
     void* fields = static_cast<char*>(workspace) + bpm::plan_bytes(nx, ny);
-    const bpm::AdjointIO io{field_in, dn, grad_field_out, grad_intensity, grad_field_in,
-                            grad_spectrum_in, grad_dn};
-    return device_status(bpm::launch_adjoint(g, p, io, K, fields, s), "adjoint march");
+    bpm::AdjointIO io[bpm::kMaxFields];
+    for (int i = 0; i < n; ++i)
+        io[i] = bpm::AdjointIO{jobs[i].field_in, jobs[i].dn, jobs[i].grad_field_out,
+                               jobs[i].grad_intensity, jobs[i].grad_field_in,
+                               jobs[i].grad_spectrum_in, jobs[i].grad_dn};
+    return device_status(bpm::launch_adjoint(g, p, io, n, K, fields, s), "adjoint march");
+}
+
+int bpm_adjoint(const bpm_c64* field_in, const float* dn, int nx, int ny, int steps, double dx,
+                double dz, double wavelength, double n0, const bpm_c64* grad_field_out,
+                const float* grad_intensity, bpm_c64* grad_field_in, bpm_c64* grad_spectrum_in,
+                float* grad_dn, int checkpoint_every, void* workspace, size_t workspace_bytes,
+                void* hip_stream) {
+    const bpm_adjoint_job job{field_in,      dn,           grad_field_out, grad_intensity,
+                              grad_field_in, grad_spectrum_in, grad_dn};
+    return adjoint_run(&job, 1, nx, ny, steps, dx, dz, wavelength, n0, checkpoint_every,
+                       workspace, workspace_bytes, hip_stream);
+}
+
+int bpm_adjoint_batch(const bpm_adjoint_job* jobs, int n_fields, int nx, int ny, int steps,
+                      double dx, double dz, double wavelength, double n0, int checkpoint_every,
+                      void* workspace, size_t workspace_bytes, void* hip_stream) {
+    if (!jobs) return fail(BPM_ERR_INVALID_ARG, "jobs must be non-null");
+    if (n_fields < 1 || n_fields > BPM_MAX_LOCKSTEP_FIELDS)
+        return fail(BPM_ERR_INVALID_ARG, "n_fields=%d must be in [1, %d]", n_fields,
+                    BPM_MAX_LOCKSTEP_FIELDS);
+    return adjoint_run(jobs, n_fields, nx, ny, steps, dx, dz, wavelength, n0, checkpoint_every,
+                       workspace, workspace_bytes, hip_stream);
 }
 
 size_t bpm_fft2_workspace_size(int nx, int ny) {

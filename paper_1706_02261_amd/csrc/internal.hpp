@@ -101,8 +101,12 @@ struct AdjointIO {
     float* grad_dn;           // or nullptr
 };
 size_t adjoint_fields(int steps, int K);
-hipError_t launch_adjoint(const Geom& g, const Plan& p, const AdjointIO& io, int K, void* fields,
-                          hipStream_t s);
+// bytes of one field's checkpoints and work fields (256-byte aligned)
+size_t adjoint_field_bytes(int nx, int ny, int steps, int K);
+// n (1 .. kMaxFields) adjoints of one geometry in lockstep; `fields` holds n
+// consecutive blocks of adjoint_field_bytes
+hipError_t launch_adjoint(const Geom& g, const Plan& p, const AdjointIO* io, int n, int K,
+                          void* fields, hipStream_t s);
 
 // Natural-order 2-D DFT (exp(-) forward, exp(+) inverse, unnormalised, times
 // `scale`); needs a plan built with or without the propagator.

@@ -465,18 +465,48 @@ size_t adjoint_fields(int steps, int K) {
     return (size_t)C + 2 * (size_t)K + 2;
 }
 
-hipError_t launch_adjoint(const Geom& g, const Plan& p, const AdjointIO& io, int K, void* fields,
-                          hipStream_t s) {
+size_t adjoint_field_bytes(int nx, int ny, int steps, int K) {
+    return align_up(sizeof(float2) * (size_t)nx * ny * adjoint_fields(steps, K));
+}
+
+hipError_t launch_adjoint(const Geom& g, const Plan& p, const AdjointIO* io, int n, int K,
+                          void* fields, hipStream_t s) {
     const size_t plane = (size_t)g.nx * g.ny;
     if (device_cus() <= 0) return hipErrorNoDevice;
-    float2* f = (float2*)fields;
+    if (n < 1 || n > kMaxFields) return hipErrorInvalidValue;
     const int C = (g.steps + K - 1) / K;
-    const AdjointArgs a{(const float2*)io.field_in, io.dn, (const float2*)io.grad_out,
-                        io.grad_inten, (float2*)io.grad_in, (float2*)io.grad_spec, io.grad_dn, f,
-                        f + plane, f + 2 * plane, f + (2 + (size_t)C) * plane,
-                        (const float2*)p.H, (const float2*)p.twx, (const float2*)p.twy,
-                        (const int*)p.permx, (const int*)p.permy, (unsigned*)p.counter,
-                        (unsigned*)p.status, wait_limit(), g.nx, g.ny, g.steps, K, k0dz_of(g)};
+    AdjointArgs a{};
+    bool linear = true;
+    for (int i = 0; i < n; ++i) {
+        float2* f = (float2*)((char*)fields + (size_t)i * adjoint_field_bytes(g.nx, g.ny, g.steps, K));
+        a.field_in[i] = (const float2*)io[i].field_in;
+        a.dn[i] = io[i].dn;
+        a.gout[i] = (const float2*)io[i].grad_out;
+        a.gI[i] = io[i].grad_inten;
+        a.gin[i] = (float2*)io[i].grad_in;
+        a.gspec[i] = (float2*)io[i].grad_spec;
+        a.gdn[i] = io[i].grad_dn;
+        a.fwork[i] = f;
+        a.gwork[i] = f + plane;
+        a.ckpt[i] = f + 2 * plane;
+        a.seg[i] = f + (2 + (size_t)C) * plane;
+        linear = linear && !io[i].grad_inten && !io[i].grad_dn;
+    }
+    a.H = (const float2*)p.H;
+    a.twx = (const float2*)p.twx;
+    a.twy = (const float2*)p.twy;
+    a.permx = (const int*)p.permx;
+    a.permy = (const int*)p.permy;
+    a.counter = (unsigned*)p.counter;
+    a.status = (unsigned*)p.status;
+    a.limit = wait_limit();
+    a.nx = g.nx;
+    a.ny = g.ny;
+    a.steps = g.steps;
+    a.K = K;
+    a.fields = n;
+    a.linear = linear ? 1 : 0;
+    a.k0dz = k0dz_of(g);
     return dispatch_nx(g.nx, [&](auto xc) {
         constexpr int NX = decltype(xc)::value;
         return launch_adjoint_x<NX>(a, s);

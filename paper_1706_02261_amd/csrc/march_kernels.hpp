@@ -388,22 +388,27 @@ __global__ __launch_bounds__(kBlock, 1) void march_adapted_kernel(AdaptArgs a) {
 //      shares the passes of these adjoint steps; the adjoint state crosses
 //      segments in `gwork`;
 //   3. a tail row pass brings g_0 back to natural order.
-// Memory: ceil(N/K) + 2 K + 2 fields (K + 2 more than the checkpoints and
-// one segment); compute: about three forward marches in about two marches'
-// worth of passes.
+// Memory per field: ceil(N/K) + 2 K + 2 fields (K + 2 more than the
+// checkpoints and one segment); compute: about three forward marches in
+// about two marches' worth of passes.
+//
+// Up to kMaxFields adjoints of one geometry (one plan, one step count and
+// checkpoint interval) run in lockstep: every pass covers the units of all
+// fields, so they share each grid barrier.  Combined unit u is unit u / F of
+// field u % F; with one field this is the single-field unit order.
 
 struct AdjointArgs {
-    const float2* field_in;
-    const float* dn;
-    const float2* gout;  // dL/du_N or null
-    const float* gI;     // dL/dI or null
-    float2* gin;         // dL/du_0 or null
-    float2* gspec;       // dL/dU_0 or null
-    float* gdn;          // dL/ddn or null
-    float2* fwork;
-    float2* gwork;
-    float2* ckpt;  // [ceil(N/K)] fields (slot 0 unused: u_0 is field_in)
-    float2* seg;   // [2 K] fields: two segment buffers
+    const float2* field_in[kMaxFields];
+    const float* dn[kMaxFields];
+    const float2* gout[kMaxFields];  // dL/du_N or null
+    const float* gI[kMaxFields];     // dL/dI or null
+    float2* gin[kMaxFields];         // dL/du_0 or null
+    float2* gspec[kMaxFields];       // dL/dU_0 or null
+    float* gdn[kMaxFields];          // dL/ddn or null
+    float2* fwork[kMaxFields];
+    float2* gwork[kMaxFields];
+    float2* ckpt[kMaxFields];  // [ceil(N/K)] fields (slot 0 unused: u_0 is field_in)
+    float2* seg[kMaxFields];   // [2 K] fields: two segment buffers
     const float2* H;
     const float2* twx;
     const float2* twy;
@@ -412,7 +417,8 @@ struct AdjointArgs {
     unsigned* counter;
     unsigned* status;
     unsigned limit;
-    int nx, ny, steps, K;
+    int nx, ny, steps, K, fields;
+    int linear;  // no field takes intensity or dn gradients
     float k0dz;
 };
 
@@ -426,7 +432,7 @@ __global__ __launch_bounds__(BLK) void adjoint_kernel(AdjointArgs a) {
     const int rows_u = (a.ny + units_per_block<NX, BLK>() - 1) / units_per_block<NX, BLK>();
     const int cols_u = (a.nx + units_per_block<NY, BLK>() - 1) / units_per_block<NY, BLK>();
     const size_t plane = (size_t)a.nx * a.ny;
-    const int N = a.steps, K = a.K, C = (N + K - 1) / K;
+    const int N = a.steps, K = a.K, C = (N + K - 1) / K, F = a.fields;
     unsigned nbar = 0;
     bool abort = false;
     Twiddles<NX, kR> twx;
@@ -436,38 +442,42 @@ __global__ __launch_bounds__(BLK) void adjoint_kernel(AdjointArgs a) {
     float d[kR];
     for (int i = 0; i < kR; ++i) d[i] = 0.f;
 
-    auto col_pass = [&](float2* work, bool conj, float2* spec_out) {
-        for (int u = v; u < cols_u; u += G) {
-            if (conj)
-                col_unit<NY, true, BLK>(u, a.nx, work, a.H, twy, smem, spec_out, a.permx, a.permy);
-            else
-                col_unit<NY, false, BLK>(u, a.nx, work, a.H, twy, smem, nullptr, nullptr, nullptr);
-        }
-    };
-
     // Without intensity and dn gradients the adjoint is the linear map M^H
     // applied to gout: the adjoint steps read no forward field, so the
     // checkpoint march and the segment recomputes are skipped.
-    const bool linear = !a.gI && !a.gdn;
+    const bool linear = a.linear != 0;
 
-    // 1. checkpoints u_K, u_2K, ..., u_(C-1)K
+    // 1. checkpoints u_K, u_2K, ..., u_(C-1)K.  A field without a forward
+    // field (a linear job among others) has no forward units: its adjoint
+    // steps read no u.
     if (C > 1 && !linear) {
-        RowArgs ra{a.field_in, a.fwork, nullptr, nullptr, nullptr, nullptr, nullptr, a.k0dz};
-        for (int u = v; u < rows_u; u += G)
-            row_unit<NX, kNaturalIn, kNoOps, kSpecOut, BLK>(u, a.ny, ra, d, twx, smem);
-        ra.src = a.fwork;
+        for (int u = v; u < rows_u * F; u += G) {
+            const int f = u % F;
+            if (!a.field_in[f]) continue;
+            const RowArgs ra{a.field_in[f], a.fwork[f], nullptr, nullptr, nullptr, nullptr,
+                             nullptr, a.k0dz};
+            row_unit<NX, kNaturalIn, kNoOps, kSpecOut, BLK>(u / F, a.ny, ra, d, twx, smem);
+        }
         const int last = (C - 1) * K;
         for (int j = 0; j < last; ++j) {
             grid_sync(a.counter, ++nbar, abort, a.status, a.limit);
-            col_pass(a.fwork, false, nullptr);
+            for (int u = v; u < cols_u * F; u += G)
+                if (a.field_in[u % F])
+                    col_unit<NY, false, BLK>(u / F, a.nx, a.fwork[u % F], a.H, twy, smem, nullptr,
+                                             nullptr, nullptr);
             grid_sync(a.counter, ++nbar, abort, a.status, a.limit);
-            ra.keep = ((j + 1) % K == 0) ? a.ckpt + (size_t)((j + 1) / K) * plane : nullptr;
-            for (int u = v; u < rows_u; u += G) {
-                load_dn<NX, BLK>(d, u, a.ny, a.dn + j * plane);
+            for (int u = v; u < rows_u * F; u += G) {
+                const int f = u % F;
+                if (!a.field_in[f]) continue;
+                const RowArgs ra{a.fwork[f], a.fwork[f], nullptr,
+                                 ((j + 1) % K == 0) ? a.ckpt[f] + (size_t)((j + 1) / K) * plane
+                                                    : nullptr,
+                                 nullptr, nullptr, nullptr, a.k0dz};
+                load_dn<NX, BLK>(d, u / F, a.ny, a.dn[f] + j * plane);
                 if (j + 1 < last)
-                    row_unit<NX, kSpecIn, kScreen, kSpecOut, BLK>(u, a.ny, ra, d, twx, smem);
+                    row_unit<NX, kSpecIn, kScreen, kSpecOut, BLK>(u / F, a.ny, ra, d, twx, smem);
                 else
-                    row_unit<NX, kSpecIn, kScreen, kNoOut, BLK>(u, a.ny, ra, d, twx, smem);
+                    row_unit<NX, kSpecIn, kScreen, kNoOut, BLK>(u / F, a.ny, ra, d, twx, smem);
             }
         }
     }
@@ -479,77 +489,84 @@ __global__ __launch_bounds__(BLK) void adjoint_kernel(AdjointArgs a) {
     // step, last step first) and read that buffer.  The recompute of segment
     // c - 1 runs in the same passes as the adjoint steps of segment c (the
     // other buffer, the other work field), so one grid barrier serves both.
-    auto seg_of = [&](int c) { return a.seg + (size_t)(c & 1) * K * plane; };
+    auto seg_of = [&](int f, int c) { return a.seg[f] + (size_t)(c & 1) * K * plane; };
     auto len_of = [&](int c) { return N - c * K < K ? N - c * K : K; };
-    // units of pass i: recompute: 0 head row, odd column, even row;
-    // adjoint: even row, odd column
-    auto rec_units = [&](int i) { return i % 2 == 0 ? rows_u : cols_u; };
-    auto adj_units = [&](int i) { return i % 2 == 0 ? rows_u : cols_u; };
-    auto rec_unit = [&](int c, int i, int u) {
+    // units of pass i (per field): recompute: 0 head row, odd column, even
+    // row; adjoint: even row, odd column
+    auto pass_units = [&](int i) { return i % 2 == 0 ? rows_u : cols_u; };
+    auto rec_unit = [&](int c, int i, int f, int u) {
+        if (!a.field_in[f]) return;
         if (i == 0) {
-            RowArgs fr{c == 0 ? a.field_in : a.ckpt + (size_t)c * plane, a.fwork, nullptr,
-                       nullptr, nullptr, nullptr, nullptr, a.k0dz};
+            const RowArgs fr{c == 0 ? a.field_in[f] : a.ckpt[f] + (size_t)c * plane, a.fwork[f],
+                             nullptr, nullptr, nullptr, nullptr, nullptr, a.k0dz};
             row_unit<NX, kNaturalIn, kNoOps, kSpecOut, BLK>(u, a.ny, fr, d, twx, smem);
         } else if (i % 2 == 1) {
-            col_unit<NY, false, BLK>(u, a.nx, a.fwork, a.H, twy, smem, nullptr, nullptr, nullptr);
+            col_unit<NY, false, BLK>(u, a.nx, a.fwork[f], a.H, twy, smem, nullptr, nullptr,
+                                     nullptr);
         } else {
             const int t = i / 2 - 1;
-            RowArgs fr{a.fwork, a.fwork, nullptr, seg_of(c) + (size_t)t * plane, nullptr,
-                       nullptr, nullptr, a.k0dz};
-            load_dn<NX, BLK>(d, u, a.ny, a.dn + (size_t)(c * K + t) * plane);
+            const RowArgs fr{a.fwork[f], a.fwork[f], nullptr, seg_of(f, c) + (size_t)t * plane,
+                             nullptr, nullptr, nullptr, a.k0dz};
+            load_dn<NX, BLK>(d, u, a.ny, a.dn[f] + (size_t)(c * K + t) * plane);
             if (t + 1 < len_of(c))
                 row_unit<NX, kSpecIn, kScreen, kSpecOut, BLK>(u, a.ny, fr, d, twx, smem);
             else
                 row_unit<NX, kSpecIn, kScreen, kNoOut, BLK>(u, a.ny, fr, d, twx, smem);
         }
     };
-    auto adj_unit = [&](int c, int i, int u) {
+    auto adj_unit = [&](int c, int i, int f, int u) {
         const int s = len_of(c) - 1 - i / 2, j = c * K + s;
         if (i % 2 == 0) {
-            RowArgs br{a.gwork, a.gwork, nullptr, nullptr, seg_of(c) + (size_t)s * plane,
-                       a.gI ? a.gI + (size_t)j * plane : nullptr,
-                       a.gdn ? a.gdn + (size_t)j * plane : nullptr, a.k0dz};
-            load_dn<NX, BLK>(d, u, a.ny, a.dn + (size_t)j * plane);
+            RowArgs br{a.gwork[f], a.gwork[f], nullptr, nullptr, seg_of(f, c) + (size_t)s * plane,
+                       a.gI[f] ? a.gI[f] + (size_t)j * plane : nullptr,
+                       a.gdn[f] ? a.gdn[f] + (size_t)j * plane : nullptr, a.k0dz};
+            load_dn<NX, BLK>(d, u, a.ny, a.dn[f] + (size_t)j * plane);
             if (j + 1 < N) {
                 row_unit<NX, kSpecIn, kAdjointOps, kSpecOut, BLK>(u, a.ny, br, d, twx, smem);
-            } else if (a.gout) {
-                br.src = a.gout;
+            } else if (a.gout[f]) {
+                br.src = a.gout[f];
                 row_unit<NX, kNaturalIn, kAdjointOps, kSpecOut, BLK>(u, a.ny, br, d, twx, smem);
             } else {
                 row_unit<NX, kZeroIn, kAdjointOps, kSpecOut, BLK>(u, a.ny, br, d, twx, smem);
             }
         } else {
-            col_unit<NY, true, BLK>(u, a.nx, a.gwork, a.H, twy, smem, j == 0 ? a.gspec : nullptr,
-                                    a.permx, a.permy);
+            col_unit<NY, true, BLK>(u, a.nx, a.gwork[f], a.H, twy, smem,
+                                    j == 0 ? a.gspec[f] : nullptr, a.permx, a.permy);
         }
     };
     // the last segment's recompute alone, then adjoint c with recompute c - 1
     if (!linear) {
         for (int i = 0; i < 2 * len_of(C - 1) + 1; ++i) {
             grid_sync(a.counter, ++nbar, abort, a.status, a.limit);
-            for (int u = v; u < rec_units(i); u += G) rec_unit(C - 1, i, u);
+            for (int u = v; u < pass_units(i) * F; u += G) rec_unit(C - 1, i, u % F, u / F);
         }
     }
     for (int c = C - 1; c >= 0; --c) {
         const int PA = 2 * len_of(c), PR = c > 0 && !linear ? 2 * len_of(c - 1) + 1 : 0;
         for (int i = 0; i < (PA > PR ? PA : PR); ++i) {
             grid_sync(a.counter, ++nbar, abort, a.status, a.limit);
-            const int na = i < PA ? adj_units(i) : 0, nr = i < PR ? rec_units(i) : 0;
+            const int na = i < PA ? pass_units(i) * F : 0, nr = i < PR ? pass_units(i) * F : 0;
             for (int u = v; u < na + nr; u += G) {
                 if (u < na)
-                    adj_unit(c, i, u);
+                    adj_unit(c, i, u % F, u / F);
                 else
-                    rec_unit(c - 1, i, u - na);
+                    rec_unit(c - 1, i, (u - na) % F, (u - na) / F);
             }
         }
     }
 
     // 3. g_0 in natural order
-    if (a.gin) {
+    bool tail = false;
+    for (int f = 0; f < F; ++f) tail = tail || a.gin[f] != nullptr;
+    if (tail) {
         grid_sync(a.counter, ++nbar, abort, a.status, a.limit);
-        RowArgs tr{a.gwork, a.gin, nullptr, nullptr, nullptr, nullptr, nullptr, a.k0dz};
-        for (int u = v; u < rows_u; u += G)
-            row_unit<NX, kSpecIn, kNoOps, kNaturalOut, BLK>(u, a.ny, tr, d, twx, smem);
+        for (int u = v; u < rows_u * F; u += G) {
+            const int f = u % F;
+            if (!a.gin[f]) continue;
+            const RowArgs tr{a.gwork[f], a.gin[f], nullptr, nullptr, nullptr, nullptr, nullptr,
+                             a.k0dz};
+            row_unit<NX, kSpecIn, kNoOps, kNaturalOut, BLK>(u / F, a.ny, tr, d, twx, smem);
+        }
     }
 }
 
@@ -623,10 +640,25 @@ hipError_t launch_adjoint_x(const AdjointArgs& a, hipStream_t s) {
         constexpr int NY = decltype(yc)::value;
         constexpr int BLK = NX <= 512 && NY <= 512 ? 64 : kBlock;
         void* args[] = {const_cast<AdjointArgs*>(&a)};
+        // A mixed pass holds two units per field, one workgroup each.  Small
+        // fields take 64-thread workgroups, so that one field spreads over
+        // many CUs; when several fields fill every CU with 256-thread
+        // workgroups, those are faster (fewer workgroups at each barrier:
+        // 8 x 256^2 x 512 in 16.0 ms against 18.3 ms with four 64-thread
+        // workgroups per CU, 2 x 512^2 x 256 in 10.6 ms against 13.1 ms).
+        if constexpr (BLK == 64 && NX * NY >= 65536) {
+            if (persistent_grid<NX, NY, kBlock>(a.nx, a.ny, 2 * a.fields) >= device_cus())
+                return hipLaunchCooperativeKernel(
+                    reinterpret_cast<const void*>(&adjoint_kernel<NX, NY, kBlock>),
+                    dim3(persistent_grid<NX, NY, kBlock>(a.nx, a.ny, 2 * a.fields)),
+                    dim3(kBlock), args, (unsigned)persistent_lds<NX, NY, kBlock>(), s);
+        }
+        // else up to four 64-thread workgroups per CU for several small fields
+        const int per_cu = BLK == 64 && a.fields > 1 ? 4 : 1;
         return hipLaunchCooperativeKernel(
             reinterpret_cast<const void*>(&adjoint_kernel<NX, NY, BLK>),
-            dim3(persistent_grid<NX, NY, BLK>(a.nx, a.ny, 2)), dim3(BLK), args,
-            (unsigned)persistent_lds<NX, NY, BLK>(), s);
+            dim3(persistent_grid<NX, NY, BLK>(a.nx, a.ny, 2 * a.fields, per_cu)), dim3(BLK),
+            args, (unsigned)persistent_lds<NX, NY, BLK>(), s);
     });
 }
 

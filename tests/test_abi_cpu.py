@@ -124,6 +124,39 @@ def test_adjoint_validation(L):
     assert rc == B.BPM_ERR_WORKSPACE
 
 
+def test_adjoint_batch_validation(L):
+    from paper_1706_02261_amd import _lib as B
+    b = Buf()
+    one = L.bpm_adjoint_workspace_size(64, 64, 4, 0)
+    plan = L.bpm_fft2_workspace_size(64, 64)
+    # the plan once, then each field's checkpoints and work fields
+    assert L.bpm_adjoint_batch_workspace_size(1, 64, 64, 4, 0) == one
+    assert L.bpm_adjoint_batch_workspace_size(3, 64, 64, 4, 0) == plan + 3 * (one - plan)
+    assert L.bpm_adjoint_batch_workspace_size(0, 64, 64, 4, 0) == 0
+    assert L.bpm_adjoint_batch_workspace_size(9, 64, 64, 4, 0) == 0
+    assert L.bpm_adjoint_batch_workspace_size(2, 100, 64, 4, 0) == 0
+    jobs = (B.AdjointJob * 2)()
+    for k in range(2):
+        jobs[k] = B.AdjointJob(b.p, b.p, None, None, b.p, None, None)
+    ws = L.bpm_adjoint_batch_workspace_size(2, 64, 64, 4, 0)
+    for n in (0, 9):
+        rc = L.bpm_adjoint_batch(jobs, n, 64, 64, 4, 0.2, 0.2, 0.5, 1.33, 0, b.p, ws, None)
+        assert rc == B.BPM_ERR_INVALID_ARG and b"n_fields" in L.bpm_last_error()
+    rc = L.bpm_adjoint_batch(None, 2, 64, 64, 4, 0.2, 0.2, 0.5, 1.33, 0, b.p, ws, None)
+    assert rc == B.BPM_ERR_INVALID_ARG
+    rc = L.bpm_adjoint_batch(jobs, 2, 64, 64, 4, 0.2, 0.2, 0.5, 1.33, 0, b.p, ws - 1, None)
+    assert rc == B.BPM_ERR_WORKSPACE
+    # the second job asks for dn gradients without its forward field
+    jobs[1] = B.AdjointJob(None, b.p, b.p, None, b.p, None, b.p)
+    rc = L.bpm_adjoint_batch(jobs, 2, 64, 64, 4, 0.2, 0.2, 0.5, 1.33, 0, b.p, ws, None)
+    assert rc == B.BPM_ERR_INVALID_ARG and b"job 1" in L.bpm_last_error()
+    jobs[1] = B.AdjointJob(b.p, None, None, None, b.p, None, None)
+    rc = L.bpm_adjoint_batch(jobs, 2, 64, 64, 4, 0.2, 0.2, 0.5, 1.33, 0, b.p, ws, None)
+    assert rc == B.BPM_ERR_INVALID_ARG and b"dn" in L.bpm_last_error()
+    rc = L.bpm_adjoint_batch(jobs, 2, 64, 64, 4, 0.2, 0.2, 0.5, 1.33, 5, b.p, ws, None)
+    assert rc == B.BPM_ERR_INVALID_ARG and b"checkpoint_every" in L.bpm_last_error()
+
+
 def test_batch_validation(L):
     from paper_1706_02261_amd import _lib as B
     b = Buf()

@@ -239,3 +239,105 @@ def test_pupil_helpers():
     G = (rng.standard_normal(spec.shape) + 1j * rng.standard_normal(spec.shape)).astype(np.complex64)
     gp = cpu(bpm.pupil_phase_grad(to_gpu(G, np.complex64), to_gpu(spec, np.complex64)))
     assert np.abs(gp - np.imag(G * np.conj(spec))).max() <= 1e-5
+
+
+def batch_case(nx, ny, steps, seed):
+    """Jobs of one geometry with different gradient requests: the full
+    adjoint, a field-only loss with dn gradients, an intensity-only loss, and
+    a linear job (no forward field)."""
+    rng = np.random.default_rng(seed)
+    jobs = []
+    for k in range(4):
+        u0, w, gI, dn = rand_case(nx, ny, steps, seed=seed * 10 + k)
+        jobs.append(dict(field=u0, dn=dn, grad_field_out=w if k != 2 else None,
+                         grad_intensity=gI if k in (0, 2) else None,
+                         want_spectrum=True, want_dn=k != 3))
+    jobs[3]["field"] = None
+    rng.shuffle(jobs)
+    return jobs
+
+
+def gpu_jobs(jobs):
+    out = []
+    for j in jobs:
+        g = dict(j)
+        g["dn"] = to_gpu(j["dn"], np.float32)
+        for key in ("field", "grad_field_out"):
+            if j.get(key) is not None:
+                g[key] = to_gpu(j[key], np.complex64)
+        if j.get("grad_intensity") is not None:
+            g["grad_intensity"] = to_gpu(j["grad_intensity"], np.float32)
+        out.append(g)
+    return out
+
+
+def separate(jobs, ck=0):
+    import paper_1706_02261_amd as bpm
+    res = []
+    for j in jobs:
+        res.append(bpm.adjoint(j.get("field"), j["dn"], 0.2, 0.2, LAM, N0,
+                               grad_field_out=j.get("grad_field_out"),
+                               grad_intensity=j.get("grad_intensity"),
+                               want_spectrum=j.get("want_spectrum", False),
+                               want_dn=j.get("want_dn", True), checkpoint_every=ck))
+    torch.cuda.synchronize()
+    return res
+
+
+def same(a, b):
+    return (a is None and b is None) or torch.equal(a, b)
+
+
+@pytest.mark.parametrize("nx,ny,steps,n,ck", [(256, 256, 40, 4, 0), (64, 128, 9, 3, 2),
+                                              (1024, 64, 6, 2, 0), (128, 128, 1, 4, 1),
+                                              (256, 256, 12, 8, 5)])
+def test_adjoint_batch_equals_separate_calls(nx, ny, steps, n, ck):
+    """Lockstep adjoints of several fields give the bits of separate calls,
+    for mixed gradient requests (full, field-only, intensity-only, linear)."""
+    import paper_1706_02261_amd as bpm
+    cases = batch_case(nx, ny, steps, seed=nx + steps + n)
+    jobs = gpu_jobs([cases[k % 4] for k in range(n)])
+    got = bpm.adjoint_batch(jobs, 0.2, 0.2, LAM, N0, checkpoint_every=ck)
+    torch.cuda.synchronize()
+    ref = separate(jobs, ck)
+    for k, (g, r) in enumerate(zip(got, ref)):
+        assert all(same(a, b) for a, b in zip(g, r)), k
+
+
+def test_adjoint_batch_linear_jobs_match_oracle():
+    """A batch of linear jobs only (no forward field, no dn gradient) takes
+    the linear path; each job agrees with the oracle's M^H and with its
+    separate call bit for bit."""
+    import paper_1706_02261_amd as bpm
+    nx, ny, steps = 128, 64, 12
+    jobs, cases = [], []
+    for k in range(3):
+        u0, w, gI, dn = rand_case(nx, ny, steps, seed=70 + k)
+        cases.append((u0, w, dn))
+        jobs.append(dict(dn=to_gpu(dn, np.float32), grad_field_out=to_gpu(w, np.complex64),
+                         want_dn=False, want_spectrum=True))
+    got = bpm.adjoint_batch(jobs, 0.2, 0.2, LAM, N0)
+    torch.cuda.synchronize()
+    ref = separate(jobs)
+    for k, ((g0, gs, gdn), (r0, rs, rdn)) in enumerate(zip(got, ref)):
+        assert gdn is None and torch.equal(g0, r0) and torch.equal(gs, rs)
+        u0, w, dn = cases[k]
+        o0, os_, _ = oracle.bpm_adjoint(u0, dn, 0.2, 0.2, LAM, N0, grad_u_out=w,
+                                        grad_intensity=None)
+        assert rel(cpu(g0), o0) <= 2e-5 and rel(cpu(gs), os_) <= 2e-5
+
+
+def test_adjoint_batch_zero_steps():
+    """Zero steps: g_0 = dL/du_N for every job (and its spectrum)."""
+    import paper_1706_02261_amd as bpm
+    rng = np.random.default_rng(5)
+    ws = [(rng.standard_normal((32, 64)) + 1j * rng.standard_normal((32, 64))).astype(np.complex64)
+          for _ in range(2)]
+    jobs = [dict(field=to_gpu(w, np.complex64), dn=torch.zeros((0, 32, 64), device="cuda"),
+                 grad_field_out=to_gpu(w, np.complex64), want_spectrum=True) for w in ws]
+    got = bpm.adjoint_batch(jobs, 0.2, 0.2, LAM, N0)
+    torch.cuda.synchronize()
+    for (g0, gs, gdn), w in zip(got, ws):
+        assert np.array_equal(cpu(g0), w)
+        assert rel(cpu(gs), np.fft.fft2(w) / w.size) <= 1e-6
+        assert gdn.shape == (0, 32, 64)
