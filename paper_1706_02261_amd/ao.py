@@ -55,6 +55,21 @@ def guide_star_gradient(dn: torch.Tensor, focus, optics: Optics = Optics(), ws=N
     return gs
 
 
+def guide_star_gradients(dn: torch.Tensor, foci, optics: Optics = Optics()):
+    """``guide_star_gradient`` of several foci through the same ``dn``, the
+    adjoints of up to eight guide stars in each lockstep launch (bitwise the
+    separate results).  Returns one G per focus."""
+    _need(dn, "dn", torch.float32)
+    _, ny, nx = dn.shape
+    out = []
+    for i in range(0, len(foci), 8):
+        jobs = [dict(dn=dn, grad_field_out=_point(ny, nx, f, dn.device), want_field=False,
+                     want_spectrum=True, want_dn=False) for f in foci[i:i + 8]]
+        out += [gs for _, gs, _ in _bpm.adjoint_batch(jobs, optics.dx, optics.dz,
+                                                      optics.wavelength, optics.n0)]
+    return out
+
+
 def guide_star_phase(dn: torch.Tensor, focus, z_focus: float, optics: Optics = Optics(),
                      shift=(0.0, 0.0)):
     """Corrected pupil phase phi* = arg G + kz z_focus (minus the tilt of a

@@ -319,6 +319,9 @@ __global__ __launch_bounds__(kBlock, 1) void march_adapted_kernel(AdaptArgs a) {
     }
     const double kPi = 3.14159265358979323846;
     const double k0 = 2.0 * kPi / a.lam;
+    // transverse wave numbers per frequency index (one division per kernel,
+    // not one per sample and step)
+    const double kxs = 2.0 * kPi / (a.nx * a.dx), kys = 2.0 * kPi / (a.ny * a.dx);
     const float scale = (float)(1.0 / ((double)a.nx * (double)a.ny));
     const int w = threadIdx.x % W, t = threadIdx.x / W;
     for (int j = 0; j < a.steps; ++j) {
@@ -331,13 +334,13 @@ __global__ __launch_bounds__(kBlock, 1) void march_adapted_kernel(AdaptArgs a) {
             const int c = u * W + w;
             const int m = a.permx[c < a.nx ? c : 0];
             const long ms = m < a.nx / 2 ? m : m - a.nx;
-            const double kx = 2.0 * kPi * (double)ms / (a.nx * a.dx);
+            const double kx = kxs * (double)ms;
             const double a2 = (double)(ms * a.ny) * (double)(ms * a.ny);
 #pragma unroll
             for (int r = 0; r < kR; ++r) {
                 const int l = a.permy[r * T + t];
                 const long ls = l < a.ny / 2 ? l : l - a.ny;
-                const double ky = 2.0 * kPi * (double)ls / (a.ny * a.dx);
+                const double ky = kys * (double)ls;
                 const double b2 = (double)(ls * a.nx) * (double)(ls * a.nx);
                 float2 hv = make_float2(0.f, 0.f);
                 if (a2 + b2 <= thr) {

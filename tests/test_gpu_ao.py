@@ -120,6 +120,22 @@ def test_guide_star_correction(tissue):
     assert inten[f] >= 4 * unc[f] and inten[f] >= 0.5 * clear[f]
 
 
+def test_guide_star_gradients_of_several_foci(tissue):
+    """Ten guide stars (two lockstep launches of 8 and 2): bitwise the single
+    adjoints, and the oracle's G for two of them."""
+    from paper_1706_02261_amd import ao
+    g = tissue["g"]
+    opt = optics_of(g)
+    foci = [(100 + 6 * k, 90 + 9 * k) for k in range(10)]
+    many = ao.guide_star_gradients(tissue["dn_t"], foci, opt)
+    assert len(many) == len(foci)
+    for f, gs in zip(foci, many):
+        assert torch.equal(gs, ao.guide_star_gradient(tissue["dn_t"], f, opt))
+    for k in (0, 9):
+        ref = oao.guide_star_gradient(tissue["dn64"], foci[k], g.dx, g.dz, g.wavelength, g.n0)
+        assert rel(cpu(many[k]), ref) <= 2e-5
+
+
 def test_focus_gradient_two_foci(tissue):
     from paper_1706_02261_amd import ao
     g, zf = tissue["g"], tissue["zf"]
