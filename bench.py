@@ -699,6 +699,8 @@ def main():
                     help="surrogate training time of the PSF block (default 60)")
     ap.add_argument("--psf-only", action="store_true",
                     help="only the surrogate vs BPM PSF rates (for profiling those kernels)")
+    ap.add_argument("--batch-only", action="store_true",
+                    help="only the uneven-batch rate (for profiling the work-queue kernel)")
     ap.add_argument("--no-extra", action="store_true",
                     help="skip the adjoint and uneven-batch rates")
     ap.add_argument("--tune", action="store_true",
@@ -729,6 +731,10 @@ def main():
     if args.psf_only:
         print(json.dumps({"metric": "surrogate vs BPM PSFs/s",
                           "psf": psf_rates(dev, train_seconds=args.train_seconds)}), flush=True)
+        return
+    if args.batch_only:
+        print(json.dumps({"metric": "uneven batch Gvoxel-steps/s",
+                          "uneven_batch": batch_rate(dev, replays=1)}), flush=True)
         return
     t_gen = time.perf_counter()
     g, u0, dn_host = synth.config2_detection(steps=args.slices)

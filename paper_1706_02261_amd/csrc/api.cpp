@@ -329,7 +329,7 @@ int batch_tables(const bpm_job* jobs, int n_jobs, char* ws, const BatchLayout& L
         dj[i] = bpm::BatchJob{j.field_in, j.dn, j.field_out, j.intensity_out, p.H, p.twx, p.twy,
                               j.nx, j.ny, j.steps,
                               (float)(2.0 * 3.14159265358979323846 / j.wavelength * j.dz),
-                              j.clear_steps};
+                              j.clear_steps, bpm::batch_tiled(j.nx, j.ny) ? 1 : 0};
     }
     // segment table: round r holds pass r of every job that has it, jobs of
     // equal pass size side by side
@@ -400,7 +400,9 @@ int batch_device(const bpm_job* jobs, int n_jobs, char* ws, const BatchLayout& L
         const bpm::Plan p = bpm::plan_carve(ws + L.plan_off[i], j.nx, j.ny);
         if (j.steps > 0) {
             const bpm::Geom g{j.nx, j.ny, j.steps, j.dx, j.dz, j.wavelength, j.n0};
-            if ((rc = device_status(bpm::launch_plan(g, p, true, s), "batch plan"))) return rc;
+            if ((rc = device_status(bpm::launch_plan(g, p, true, s, bpm::batch_tiled(j.nx, j.ny)),
+                                    "batch plan")))
+                return rc;
         } else if ((const void*)j.field_out != (const void*)j.field_in) {
             hipError_t e = hipMemcpyAsync(j.field_out, j.field_in,
                                           sizeof(bpm_c64) * (size_t)j.nx * j.ny,

@@ -18,6 +18,7 @@
 
 #include "internal.hpp"
 #include "passes.hpp"
+#include "tiled.hpp"
 
 namespace bpm {
 
@@ -122,6 +123,114 @@ __device__ __attribute__((noinline)) void batch_col(g_float2* work_g, const g_fl
     }
 }
 
+// The same row and column items for a job kept in the tiled layout of
+// tiled.hpp between its passes (batch_tiled): the column pass of a
+// 1024-long column then reads and writes whole lines instead of a quarter
+// of each.  The head row pass converts natural -> tiled and the last row pass
+// tiled -> natural in place, as in the tiled march.  In the tiled mapping a
+// row or column spans every wavefront of the workgroup, so a workgroup
+// barrier precedes each unit's transforms: the previous unit's last LDS
+// reads (other wavefronts, possibly another layout of the slots) are done
+// before this unit's first LDS writes.
+template <int NX, int NY>
+__device__ __attribute__((noinline)) void batch_trow(const g_float2* field_in, g_float2* work_g,
+                                                     const g_float* dn, g_float* inten,
+                                                     const g_float2* twx, int steps, float k0dz,
+                                                     int clear, int pass, int item,
+                                                     lds_float2* lds) {
+    using TL = Tiles<NX, NY>;
+    float2* smem = (float2*)lds;
+    float2* work = (float2*)work_g;
+    OpaqueTwiddles<NX, kR> tw;
+    tw.load((const float2*)twx, threadIdx.x / TL::B);
+    constexpr int units = NY / TL::B;
+    constexpr size_t plane = (size_t)NX * NY;
+    const int s = pass / 2 - 1;
+    for (int u0 = item * kUnitsPerItem; u0 < units && u0 < (item + 1) * kUnitsPerItem; u0 += 2) {
+        const int u1 = u0 + 1;
+        const bool two = u1 < units;
+        float d0[kR], d1[kR];
+        float2 va[kR], vb[kR];
+        if (pass == 0) {
+#pragma unroll
+            for (int i = 0; i < kR; ++i) d0[i] = 0.f;
+            const RowArgs ra{(const float2*)field_in, work, nullptr, nullptr, nullptr, nullptr,
+                             nullptr, k0dz};
+            trow_load<NX, NY, kNaturalIn>(u0, ra.src, va);
+            if (two) trow_load<NX, NY, kNaturalIn>(u1, ra.src, vb);
+            __syncthreads();
+            trow_body<NX, NY, kNaturalIn, kNoOps, kSpecOut>(u0, ra, d0, tw, smem, va);
+            if (two) {
+                __syncthreads();
+                trow_body<NX, NY, kNaturalIn, kNoOps, kSpecOut>(u1, ra, d0, tw, smem, vb);
+            }
+            continue;
+        }
+        const float* dns = (const float*)dn + s * plane;
+        const RowArgs ra{work, work, inten ? (float*)inten + s * plane : nullptr, nullptr,
+                         nullptr, nullptr, nullptr, k0dz};
+        trow_load<NX, NY, kSpecIn>(u0, ra.src, va);
+        if (s >= clear)
+            trow_dn<NX, NY>(u0, dns, d0);
+        else
+            zero_dn(d0);
+        if (two) {
+            trow_load<NX, NY, kSpecIn>(u1, ra.src, vb);
+            if (s >= clear)
+                trow_dn<NX, NY>(u1, dns, d1);
+            else
+                zero_dn(d1);
+        }
+        __syncthreads();
+        if (s + 1 < steps)
+            trow_body<NX, NY, kSpecIn, kScreen, kSpecOut>(u0, ra, d0, tw, smem, va);
+        else
+            trow_body<NX, NY, kSpecIn, kScreen, kNaturalOut>(u0, ra, d0, tw, smem, va);
+        if (two) {
+            __syncthreads();
+            if (s + 1 < steps)
+                trow_body<NX, NY, kSpecIn, kScreen, kSpecOut>(u1, ra, d1, tw, smem, vb);
+            else
+                trow_body<NX, NY, kSpecIn, kScreen, kNaturalOut>(u1, ra, d1, tw, smem, vb);
+        }
+    }
+}
+
+template <int NX, int NY>
+__device__ __attribute__((noinline)) void batch_tcol(g_float2* work_g, const g_float2* H_g,
+                                                     const g_float2* twy, int item,
+                                                     lds_float2* lds) {
+    using TL = Tiles<NX, NY>;
+    float2* smem = (float2*)lds;
+    float2* work = (float2*)work_g;
+    const float2* H = (const float2*)H_g;
+    OpaqueTwiddles<NY, kR> tw;
+    tw.load((const float2*)twy, threadIdx.x / TL::W);
+    constexpr int units = NX / TL::W;
+    for (int u0 = item * kUnitsPerItem; u0 < units && u0 < (item + 1) * kUnitsPerItem; u0 += 2) {
+        const int u1 = u0 + 1;
+        const bool two = u1 < units;
+        float2 va[kR], ha[kR], vb[kR], hb[kR];
+        tcol_load<NX, NY>(u0, work, va);
+        tcol_h<NX, NY>(u0, H, ha);
+        if (two) {
+            tcol_load<NX, NY>(u1, work, vb);
+            tcol_h<NX, NY>(u1, H, hb);
+        }
+        __syncthreads();
+        tcol_body<NX, NY>(u0, work, tw, smem, va, ha);
+        if (two) {
+            __syncthreads();
+            tcol_body<NX, NY>(u1, work, tw, smem, vb, hb);
+        }
+    }
+}
+
+bool batch_tiled(int nx, int ny) { return ny >= 1024 && nx >= 256 && (long)nx * ny <= (1L << 20); }
+
+// (nx, ny) of the tiled jobs, as one switch key
+constexpr int tkey(int nx, int ny) { return nx * 4096 + ny; }
+
 __global__ __launch_bounds__(kBlock) void batch_kernel(const BatchJob* __restrict__ jobs,
                                                        const BatchSeg* __restrict__ segs,
                                                        int total, unsigned* q,
@@ -164,7 +273,27 @@ __global__ __launch_bounds__(kBlock) void batch_kernel(const BatchJob* __restric
             }
         }
         __syncthreads();
-        if (sg.pass % 2 == 0) {
+        if (jb.tiled) {
+#define BPM_TILED_CASE(X, Y)                                                                   \
+    case tkey(X, Y):                                                                           \
+        if (sg.pass % 2 == 0)                                                                  \
+            batch_trow<X, Y>((const g_float2*)jb.field_in, (g_float2*)jb.work,                 \
+                             (const g_float*)jb.dn, (g_float*)jb.inten, (const g_float2*)jb.twx, \
+                             jb.steps, jb.k0dz, jb.clear, sg.pass, tile, lds);                 \
+        else                                                                                   \
+            batch_tcol<X, Y>((g_float2*)jb.work, (const g_float2*)jb.H,                        \
+                             (const g_float2*)jb.twy, tile, lds);                              \
+        break;
+            switch (tkey(jb.nx, jb.ny)) {
+                BPM_TILED_CASE(256, 1024)
+                BPM_TILED_CASE(512, 1024)
+                BPM_TILED_CASE(1024, 1024)
+                BPM_TILED_CASE(256, 2048)
+                BPM_TILED_CASE(512, 2048)
+                default: break;
+            }
+#undef BPM_TILED_CASE
+        } else if (sg.pass % 2 == 0) {
             switch (jb.nx) {
                 case 32: batch_row<32>((const g_float2*)jb.field_in, (g_float2*)jb.work, (const g_float*)jb.dn,
                                                   (g_float*)jb.inten, (const g_float2*)jb.twx, jb.nx,

@@ -127,7 +127,12 @@ struct BatchJob {
     int nx, ny, steps;
     float k0dz;
     int clear;  // leading steps without a screen
+    int tiled;  // field and propagator in the tiled layout between passes
 };
+// whether the work queue keeps a job of this size in the tiled layout
+// (columns of >= 1024, nx >= 256, nx ny <= 2^20: there a column unit covers
+// less than a line of the natural layout)
+bool batch_tiled(int nx, int ny);
 struct BatchSeg {
     int job, pass, first, count, need;
 };

@@ -109,9 +109,9 @@ __global__ void plan_kernel(unsigned* __restrict__ status, float2* __restrict__ 
                 h = make_float2((float)(cv * scale), (float)(sv * scale));
             }
             if (tiled) {
-                // B x W tiles of one 128-byte line (B = 4096 / nx, W = 4096 / ny)
-                const long B = 4096 / nx, W = 4096 / ny;
-                H[((py / B) * (nx / W) + px / W) * 16 + (py % B) * W + px % W] = h;
+                // TH x W tiles of one 128-byte line (W = 4096 / ny, TH = 16 / W)
+                const long W = 4096 / ny, TH = 16 / W;
+                H[((py / TH) * (nx / W) + px / W) * 16 + (py % TH) * W + px % W] = h;
             } else {
                 H[e] = h;
             }

@@ -1,18 +1,20 @@
-// Tiled field layout between the passes of the two-field march, and the row
-// and column passes that read and write it.
+// Tiled field layout between the passes of the tiled march and of the work
+// queue's tall jobs, and the row and column passes that read and write it.
 //
-// When nx ny = 2^20 (1024^2, 2048 x 512, 512 x 2048), a row unit is B rows and
-// a column unit W columns with B W = 16, so a tile of B rows x W columns of
-// complex64 is one 128-byte line.  The field between passes is stored tile by
-// tile (tiles row-major, each tile row-major), and both passes give each
-// thread a sequence of one unit (a row, or a column) interleaved with the
-// unit's other B (or W) sequences across consecutive lanes: 16 consecutive
-// lanes then cover one whole tile, and every wavefront load or store touches
-// four whole lines, in the row pass and in the column pass alike.  (In the
-// natural [y][x] layout a column pass reaches only 32 bytes of each line.)
-// A tile row holds exactly the bytes of its B natural rows, so the head pass
-// (natural in, tiled out) and the tail pass (tiled in, natural out) convert
-// in place.
+// A column unit is W columns (W = 4096 / ny) and a row unit B rows
+// (B = 4096 / nx).  A tile is TH = 16 / W rows x W columns of complex64: one
+// 128-byte line.  The field between passes is stored tile by tile (tiles
+// row-major, each tile row-major), and both passes give each thread a
+// sequence of one unit (a row, or a column) interleaved with the unit's other
+// B (or W) sequences across consecutive lanes: consecutive lanes then cover
+// whole tiles, and every wavefront load or store touches whole lines, in the
+// row pass and in the column pass alike.  (In the natural [y][x] layout a
+// column pass of a 1024-long column reaches only 32 bytes of each line.)
+// The layout needs W <= 16 and nx ny <= 2^20, so that a row unit is a whole
+// number of tile rows (B = TH when nx ny = 2^20: 1024^2, 2048 x 512,
+// 512 x 2048).  The B rows of a row unit then hold exactly the bytes of its B
+// natural rows, so the head pass (natural in, tiled out) and the tail pass
+// (tiled in, natural out) convert in place.
 #pragma once
 
 #include "passes.hpp"
@@ -21,11 +23,13 @@ namespace bpm {
 
 template <int NX, int NY>
 struct Tiles {
-    static constexpr int B = units_per_block<NX>();  // rows of a row unit: tile height
+    static constexpr int B = units_per_block<NX>();  // rows of a row unit
     static constexpr int W = units_per_block<NY>();  // columns of a column unit: tile width
-    static_assert(B * W == 16, "a tile is one 128-byte line of complex64");
+    static constexpr int TH = 16 / W;                // tile height
+    static_assert(W <= 16 && TH * W == 16, "a tile is one 128-byte line of complex64");
+    static_assert(B % TH == 0, "a row unit is a whole number of tile rows");
     __device__ static __forceinline__ size_t off(int y, int x) {
-        return ((size_t)(y / B) * (NX / W) + x / W) * 16 + (y % B) * W + x % W;
+        return ((size_t)(y / TH) * (NX / W) + x / W) * 16 + (y % TH) * W + x % W;
     }
 };
 

@@ -60,6 +60,28 @@ def test_batch_equals_separate_calls_and_oracle():
         assert rel(o, ro) <= 2e-6 and rel(i, ri) <= 4e-6
 
 
+# columns of >= 1024 with nx >= 256 and nx ny <= 2^20 stay in the tiled layout
+# between the work queue's passes; (128, 1024) and (1024, 256) do not
+TILED_SHAPES = [(256, 1024, 5), (512, 1024, 4), (1024, 1024, 3), (256, 2048, 3),
+                (512, 2048, 2), (256, 1024, 1), (128, 1024, 3), (1024, 256, 4)]
+
+
+def test_work_queue_tiled_jobs_equal_separate_calls_and_oracle():
+    """Jobs the work queue keeps tiled between passes, one-step jobs among
+    them, next to natural-layout jobs: the bits of separate calls, and the
+    oracle within the march's tolerance."""
+    import paper_1706_02261_amd as bpm
+    jobs = make_jobs(TILED_SHAPES, seed=12)
+    res = bpm.propagate_batch(jobs)
+    torch.cuda.synchronize()
+    for job, (out, inten) in zip(jobs, res):
+        o, i = out.cpu().numpy(), inten.cpu().numpy()
+        so, si = separate(job)
+        assert np.array_equal(o, so) and np.array_equal(i, si), job["u0"].shape
+        ro, ri = oracle.bpm_forward(job["u0"], job["dn_h"], job["dx"], job["dz"], 0.5, 1.33)
+        assert rel(o, ro) <= 2e-6 and rel(i, ri) <= 4e-6, job["u0"].shape
+
+
 def test_batch_repeated_launches_on_one_workspace():
     """Queue and completion counters are reset by every launch."""
     import paper_1706_02261_amd as bpm
