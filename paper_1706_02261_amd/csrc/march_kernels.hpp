@@ -645,12 +645,14 @@ hipError_t launch_adjoint_x(const AdjointArgs& a, hipStream_t s) {
         void* args[] = {const_cast<AdjointArgs*>(&a)};
         // A mixed pass holds two units per field, one workgroup each.  Small
         // fields take 64-thread workgroups, so that one field spreads over
-        // many CUs; when several fields fill every CU with 256-thread
-        // workgroups, those are faster (fewer workgroups at each barrier:
-        // 8 x 256^2 x 512 in 16.0 ms against 18.3 ms with four 64-thread
-        // workgroups per CU, 2 x 512^2 x 256 in 10.6 ms against 13.1 ms).
+        // many CUs; when several fields fill at least half the CUs with
+        // 256-thread workgroups, those are faster (fewer workgroups at each
+        // barrier: 8 x 256^2 x 512 in 15.9 ms against 18.3 ms with four
+        // 64-thread workgroups per CU, 4 x 256^2 x 512 in 13.1 against
+        // 13.9 ms, 2 x 512^2 x 256 in 10.6 ms against 13.1 ms).
         if constexpr (BLK == 64 && NX * NY >= 65536) {
-            if (persistent_grid<NX, NY, kBlock>(a.nx, a.ny, 2 * a.fields) >= device_cus())
+            if (a.fields > 1 &&
+                persistent_grid<NX, NY, kBlock>(a.nx, a.ny, 2 * a.fields) >= device_cus() / 2)
                 return hipLaunchCooperativeKernel(
                     reinterpret_cast<const void*>(&adjoint_kernel<NX, NY, kBlock>),
                     dim3(persistent_grid<NX, NY, kBlock>(a.nx, a.ny, 2 * a.fields)),
